@@ -1,0 +1,96 @@
+"""Oracle: the HMC density step (test infrastructure only).
+
+Sec. "The HMC algorithm": with potential psi = -ln P (eq. Potential), momenta p
+and mass M, H = 1/2 p^T M^-1 p + psi (eq. Hamiltonian).  A trajectory draws
+p ~ N(0, M), integrates Hamilton's equations (eqs. HAMILTON1_a, HAMILTON2_a) with
+a leapfrog scheme and accepts with probability min(1, exp(-dH))
+(eq. acceptance_rule).
+
+Readings (the paper leaves these open):
+* the sign of eq. HAMILTON2: dp/dt = -d psi/dx, as used in eq. HAMILTON2_a;
+* leapfrog ordering kick-drift-kick (half kick, n x [drift, kick], last kick
+  halved), fixed step eps and step count n;
+* the mass is diagonal in Fourier space (m_k of ``model.mass_table``), so the
+  kinetic term is K = 1/2 sum_k |p_hat_k|^2 / m_k and p ~ N(0, M) is drawn as
+  p_hat = sqrt(m_k) F w with w real white noise (Philox stream 3);
+* the mean mode k = 0 is frozen: delta_hat_0 = p_hat_0 = 0 throughout;
+* accept iff ln u < -dH with u from Philox stream 4 (strict inequality).
+
+State variables are delta_hat (half grid) and p_hat; sums over the stored
+half grid carry the full-grid weight w_k (``grid.half_weights``).
+"""
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import grid, model, philox
+
+
+@dataclass
+class Posterior:
+    """Everything the density step holds fixed during one trajectory."""
+    n: int
+    box: float
+    nb: int
+    shells: np.ndarray
+    w: np.ndarray
+    lam_k: np.ndarray
+    mass_k: np.ndarray
+    alpha: np.ndarray
+    beta: np.ndarray
+    abar: float
+    workers: int = 1
+
+
+def make_posterior(n, box, nb, pk, R, counts, bias, nbar, workers=1):
+    shells = grid.half_shells(n, nb)
+    alpha, beta, abar = model.coefficients(R, counts, bias, nbar)
+    lam = model.lambdas(pk, n, box)
+    return Posterior(n, box, nb, shells, grid.half_weights(n), model.per_mode(lam, shells),
+                     model.per_mode(model.mass_table(lam, abar), shells), alpha, beta, abar,
+                     workers)
+
+
+def draw_momentum(post, seed, chain, traj):
+    """p_hat = sqrt(m_k) F w, w ~ N(0, 1) per voxel from Philox stream 3."""
+    n = post.n
+    wn = philox.normals(seed, chain, philox.STREAM_MOMENTA, traj, n ** 3).reshape(n, n, n)
+    wk = grid.fwd(wn, post.workers)
+    return np.where(post.shells >= 0, np.sqrt(np.where(post.shells >= 0, post.mass_k, 1.0)) * wk,
+                    0.0)
+
+
+def energies(dk, pk, delta, post):
+    """(kinetic, prior, data) parts of H for a given state."""
+    sel = post.shells >= 0
+    kin = 0.5 * np.sum((post.w * np.abs(pk) ** 2)[sel] / post.mass_k[sel])
+    pri = 0.5 * np.sum((post.w * np.abs(dk) ** 2)[sel] / post.lam_k[sel])
+    dat = model.psi_data(delta, post.alpha, post.beta)
+    return float(kin), float(pri), float(dat)
+
+
+def leapfrog(dk, pk, post, eps, nsteps):
+    """KDK integration; returns (delta_hat, p_hat, grad_hat, delta) at the end."""
+    f, gk, delta = model.force_k(dk, post.lam_k, post.alpha, post.beta, post.workers)
+    inv_m = np.where(post.shells >= 0, 1.0 / np.where(post.shells >= 0, post.mass_k, 1.0), 0.0)
+    pk = pk - 0.5 * eps * f
+    for s in range(nsteps):
+        dk = dk + eps * pk * inv_m
+        f, gk, delta = model.force_k(dk, post.lam_k, post.alpha, post.beta, post.workers)
+        pk = pk - (eps if s < nsteps - 1 else 0.5 * eps) * f
+    return dk, pk, gk, delta
+
+
+def trajectory(dk, post, eps, nsteps, seed, chain, traj):
+    """One HMC proposal + accept.  Returns a dict with the new state and dH."""
+    pk0 = draw_momentum(post, seed, chain, traj)
+    delta0 = grid.inv(dk, post.n, post.workers)
+    e0 = energies(dk, pk0, delta0, post)
+    dk1, pk1, gk1, delta1 = leapfrog(dk, pk0, post, eps, nsteps)
+    e1 = energies(dk1, pk1, delta1, post)
+    dH = sum(e1) - sum(e0)
+    u = philox.uniform(seed, chain, philox.STREAM_ACCEPT, traj)
+    acc = bool(np.log(u) < -dH)
+    return dict(p0=pk0, e0=e0, e1=e1, dH=dH, accepted=acc, log_u=float(np.log(u)),
+                proposal=dk1, p1=pk1, grad1=gk1, delta1=delta1,
+                state=dk1 if acc else dk)

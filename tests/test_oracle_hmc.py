@@ -1,0 +1,119 @@
+"""Pins for oracle.hmc: integrator properties and exactness against the dense Wiener posterior."""
+import numpy as np
+import pytest
+
+import dense
+from oracle import grid, hmc, model
+from synth import CONFIGS, make_mock
+
+
+def posterior(name="tiny8x2", delta_start=True):
+    mk = make_mock(CONFIGS[name])
+    cfg = mk["cfg"]
+    post = hmc.make_posterior(cfg.n, cfg.box, cfg.nb, mk["pk_init"], mk["R"], mk["counts"],
+                              mk["bias"], mk["nbar"])
+    dk = grid.fwd(mk["delta"]) if delta_start else np.zeros((cfg.n, cfg.n, cfg.n // 2 + 1), complex)
+    dk[0, 0, 0] = 0
+    return mk, cfg, post, dk
+
+
+def test_reversibility():
+    mk, cfg, post, dk = posterior()
+    p = hmc.draw_momentum(post, 3, 0, 0)
+    d1, p1, _, _ = hmc.leapfrog(dk, p, post, 0.1, 15)
+    d2, p2, _, _ = hmc.leapfrog(d1, -p1, post, 0.1, 15)
+    assert np.max(np.abs(d2 - dk)) < 1e-11 * np.max(np.abs(dk))
+    assert np.max(np.abs(p2 + p)) < 1e-11 * np.max(np.abs(p))
+
+
+def test_energy_error_is_second_order():
+    mk, cfg, post, dk = posterior()
+    p = hmc.draw_momentum(post, 4, 0, 0)
+    d0 = grid.inv(dk, cfg.n)
+    H0 = sum(hmc.energies(dk, p, d0, post))
+    errs = []
+    for eps, n in [(0.1, 10), (0.05, 20), (0.025, 40), (0.0125, 80)]:
+        d1, p1, _, x1 = hmc.leapfrog(dk, p, post, eps, n)
+        errs.append(abs(sum(hmc.energies(d1, p1, x1, post)) - H0))
+    slopes = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(np.abs(slopes - 2.0) < 0.1), slopes
+
+
+def test_leapfrog_equals_dense_affine_map():
+    """The FFT leapfrog equals iterating the dense affine KDK map in real space."""
+    mk, cfg, post, dk = posterior()
+    n = cfg.n
+    lam_m = model.lambdas(mk["pk_init"], n, cfg.box)
+    _, _, Q, U = dense.wiener(n, lam_m, cfg.nb, post.alpha, post.beta)
+    sh = dense.shell_full(n, cfg.nb)
+    inv_m = np.where(sh >= 0, 1.0 / model.mass_table(lam_m, post.abar)[np.maximum(sh, 0)], 0.0)
+    Minv = dense.fourier_diag_operator(n, inv_m)
+    P = U @ U.T
+    b = P @ post.beta.reshape(-1)
+    pk = hmc.draw_momentum(post, 5, 0, 0)
+    eps, steps = 0.12, 9
+    d = grid.inv(dk, n).reshape(-1)
+    p = grid.inv(pk, n).reshape(-1)
+    f = lambda x: P @ (Q @ x) - b
+    p = p - 0.5 * eps * f(d)
+    for s in range(steps):
+        d = d + eps * Minv @ p
+        p = p - (eps if s < steps - 1 else 0.5 * eps) * f(d)
+    d1, p1, _, _ = hmc.leapfrog(dk, pk, post, eps, steps)
+    assert np.max(np.abs(grid.inv(d1, n).reshape(-1) - d)) < 1e-11 * np.max(np.abs(d))
+    assert np.max(np.abs(grid.inv(p1, n).reshape(-1) - p)) < 1e-11 * np.max(np.abs(p))
+    # volume preservation: the linear part of one step has unit determinant on the subspace
+    I = np.eye(n ** 3)
+    A11 = I - eps * eps / 2 * Minv @ P @ Q
+    lin = np.block([[A11, eps * Minv],
+                    [-eps * P @ Q + eps ** 3 / 4 * P @ Q @ Minv @ P @ Q, I - eps * eps / 2 * P @ Q @ Minv]])
+    W = np.block([[U, np.zeros_like(U)], [np.zeros_like(U), U]])
+    sign, logdet = np.linalg.slogdet(W.T @ lin @ W)
+    assert sign > 0 and abs(logdet) < 1e-8
+
+
+def _ess(x):
+    """Effective sample size by Geyer's initial positive sequence (plain numpy)."""
+    x = np.asarray(x) - np.mean(x)
+    n = len(x)
+    f = np.fft.rfft(x, 2 * n)
+    ac = np.fft.irfft(f * np.conj(f))[:n] / (np.arange(n, 0, -1))
+    ac /= ac[0]
+    s = 0.0
+    for t in range(1, n // 2):
+        pair = ac[2 * t - 1] + ac[2 * t]
+        if pair < 0:
+            break
+        s += pair
+    return n / max(1.0, 1.0 + 2.0 * (s + 0.0))
+
+
+@pytest.mark.slow
+def test_chain_matches_dense_wiener_posterior():
+    """Fixed P, b, Nbar at 8^3: HMC draws have the closed-form Wiener mean and covariance."""
+    mk, cfg, post, dk = posterior()
+    n = cfg.n
+    lam_m = model.lambdas(mk["pk_init"], n, cfg.box)
+    mu, cov, Q, U = dense.wiener(n, lam_m, cfg.nb, post.alpha, post.beta)
+    evals, evecs = np.linalg.eigh(U.T @ cov @ U)
+    T = (U @ evecs) / np.sqrt(evals)            # whitening map on the subspace
+    dk = grid.fwd(mu.reshape(n, n, n))
+    samples = []
+    acc = 0
+    nsamp = 3000
+    for t in range(nsamp):
+        steps = 6 + (t % 7)                      # varied lengths avoid resonant trajectories
+        tr = hmc.trajectory(dk, post, 0.2, steps, 11, 0, t)
+        dk = tr["state"]
+        acc += tr["accepted"]
+        samples.append(grid.inv(dk, n).reshape(-1))
+    S = np.array(samples)
+    y = (S - mu) @ T                              # should be iid N(0, 1) per column
+    assert acc / nsamp > 0.6
+    ess = np.array([_ess(y[:, j]) for j in range(y.shape[1])])
+    zmean = y.mean(axis=0) * np.sqrt(ess)
+    assert np.max(np.abs(zmean)) < 5.0
+    assert abs(np.mean(zmean ** 2) - 1.0) < 0.3
+    var = y.var(axis=0)
+    assert np.max(np.abs(var - 1.0) * np.sqrt(ess / 2.0)) < 6.0
+    assert abs(var.mean() - 1.0) < 0.03
