@@ -1,0 +1,157 @@
+#!/usr/bin/env python
+"""Leapfrog steps/s of the HMC density sampler on one MI355X.
+
+A bench step is one full block sweep of the sampler (density HMC trajectory,
+P draw, joint (P, delta) move, Nbar and bias draws, coefficient and gradient
+refresh) on the 256^3 survey workload (L = 1500 Mpc/h, 6 subsamples, 60
+k-shells, 30 leapfrog steps).  `value` counts the density-HMC leapfrog steps
+completed per second of whole sweeps, inputs resident in HBM.
+
+The JSON line also carries:
+  roofline      the k-space step pass (kick, drift and both x transforms), its
+                average device duration measured with HIP events on the
+                library's stream during the timed sweeps, against 8 TB/s;
+  cpu_baseline  the float64 CPU oracle timed on this host on a bounded sample
+                of the same workload (a few leapfrog steps).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def workload_spec(name, eps):
+    from synth import CONFIGS, make_mock
+    mk = make_mock(CONFIGS[name], dtype=np.float32)
+    cfg = mk["cfg"]
+    spec = dict(n=cfg.n, box=cfg.box, nb=cfg.nb, R=mk["R"], counts=mk["counts"], bias=mk["bias"],
+                nbar=mk["nbar"], pk=mk["pk_init"], fixed_mask=cfg.fixed_mask, nsteps=cfg.nsteps,
+                eps=eps, rj=cfg.rj, seed=2013, chain_id=0)
+    return mk, spec
+
+
+def cpu_baseline(mk, spec, budget_s):
+    """Oracle leapfrog steps/s (float64, scipy.fft on all host cores)."""
+    from oracle import grid, hmc
+    workers = os.cpu_count() or 1
+    R = mk["R"].astype(np.float64)
+    C = mk["counts"].astype(np.float64)
+    post = hmc.make_posterior(spec["n"], spec["box"], spec["nb"], spec["pk"], R, C, spec["bias"],
+                              spec["nbar"], workers=workers)
+    dk = grid.fwd(mk["delta"].astype(np.float64), workers)
+    dk[0, 0, 0] = 0
+    pk = hmc.draw_momentum(post, spec["seed"], 0, 0)
+    t0 = time.perf_counter()
+    hmc.leapfrog(dk, pk, post, spec["eps"], 1)
+    t1 = time.perf_counter() - t0
+    steps = max(1, min(60, int(budget_s / max(t1, 1e-3))))
+    t0 = time.perf_counter()
+    hmc.leapfrog(dk, pk, post, spec["eps"], steps)
+    dt = time.perf_counter() - t0
+    return dict(value=steps / dt, unit="leapfrog steps/s", cores=workers, kind="oracle",
+                sample=f"{steps} float64 KDK leapfrog steps (one gradient evaluation each) of the "
+                       f"{spec['n']}^3 workload, scipy.fft workers={workers}, {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20, help="timed sweeps")
+    ap.add_argument("--warmup", type=int, default=3, help="untimed sweeps")
+    ap.add_argument("--workload", default="cfg3")
+    ap.add_argument("--eps", type=float, default=0.02)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the sampler runs on a single MI355X "
+              "(chains or slabs would shard across GPUs, which this build does not do)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1306_1821_amd.binding import Sampler
+
+    mk, spec = workload_spec(args.workload, args.eps)
+    n, nh = spec["n"], spec["n"] * spec["n"] * (spec["n"] // 2 + 1)
+    s = Sampler([spec])
+    print(f"[bench] {args.workload}: N={n} c={len(spec['bias'])} nb={spec['nb']} "
+          f"nsteps={spec['nsteps']} eps={spec['eps']}", file=sys.stderr, flush=True)
+    sweep = 0
+    for _ in range(args.warmup):
+        s.sweep(sweep)
+        sweep += 1
+    torch.cuda.synchronize()
+    s.timing(1)
+    acc, rj_acc = [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st = s.sweep(sweep)[0]
+        acc.append(st["accepted"])
+        rj_acc.append(st["rj_accepted"])
+        sweep += 1
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms, launches = s.timing(0)
+    print(f"[bench] {args.steps} sweeps in {dt:.3f} s", file=sys.stderr, flush=True)
+
+    # pure trajectory rate (leapfrog only) for reference
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ntraj = max(2, args.steps // 2)
+    for i in range(ntraj):
+        s.trajectory(10_000 + i)
+    torch.cuda.synchronize()
+    dt_traj = time.perf_counter() - t1
+
+    steps = args.steps * spec["nsteps"]
+    value = steps / dt
+    avg_ms = ms[0] / max(1, launches[0])
+    bytes_launch = 6 * nh * 8          # read T, delta_hat, p_hat; write delta_hat, p_hat, T
+    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
+    out = {
+        "metric": "leapfrog steps/s at 256^3",
+        "value": value,
+        "unit": "leapfrog steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * dt / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {n}^3 grid, L={spec['box']:.0f} Mpc/h, "
+                               f"{len(spec['bias'])} subsamples, {spec['nb']} k-shells, "
+                               f"{spec['nsteps']} leapfrog steps, joint move "
+                               f"{'on' if spec['rj'] else 'off'}; one bench step = one sweep",
+                   "eps": spec["eps"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": f"k_xpass_n<{n}, X_STEP>", "avg_ms": avg_ms,
+                     "launches": int(launches[0]), "bytes_per_launch": bytes_launch},
+        "acceptance": float(np.mean(acc)),
+        "rj_acceptance": float(np.mean(rj_acc)),
+        "trajectory_leapfrog_steps_per_s": ntraj * spec["nsteps"] / dt_traj,
+        "pass_ms_per_step": {"kspace": avg_ms,
+                             "ypass": ms[1] / max(1, launches[1]),
+                             "zpass": ms[2] / max(1, launches[2])},
+    }
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(mk, spec, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,206 @@
+/*
+ * libhmc -- HMC density sampler of Jasche & Wandelt (2013), "Methods for
+ * Bayesian power spectrum inference with galaxy surveys", on AMD MI355X.
+ *
+ * The library samples the joint posterior P(delta, S, {Nbar^l}, {b^l} | {N^l_i})
+ * of Sec. "The joint posterior distribution" with the block scheme of
+ * eq. multiblock: an HMC step for the density field (Sec. "The HMC algorithm",
+ * Sec. "Equations of motion for the Wiener Posterior"), the inverse-Gamma
+ * power-spectrum draw (eq. INVERSE_GAMMA via eq. XI_SQUARE), the GIG draw for
+ * Nbar (eq. GIG_post), the normal draw for the biases (Appendix B) and the
+ * joint (P, delta) move of Appendix C (eq. det_trans, eq.
+ * spec_posterior_MIXING_1).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Grid: N^3 voxels, N in {8, 16, 32, 64, 128, 192, 256}; real fields are
+ *    float32 row-major [x][y][z] (z fastest).
+ *  - Fourier fields are complex64 (interleaved re, im floats), layout
+ *    [kx][ky][kz] with kz in [0, N/2]: N * N * (N/2+1) complex values.  The DFT
+ *    is the Appendix "Discrete Fourier transformation" convention with the
+ *    unitary normalisation C = C_hat = N^(-3/2); kx, ky map to signed
+ *    frequencies -(N/2-1)..N/2.
+ *  - k-shells: n_bins linear shells over (0, sqrt(3) (N/2) 2 pi / L]; with
+ *    q = kx^2 + ky^2 + kz^2 (signed integer frequencies) and q_max = 3 (N/2)^2,
+ *    mode q >= 1 is in the shell m with m^2 q_max < n_bins^2 q <= (m+1)^2 q_max.
+ *    The mean mode k = 0 is in no shell and is held at zero.
+ *  - Power spectrum values P_m are in (Mpc/h)^3; the prior eigenvalue is
+ *    lambda_m = P_m N^3 / L^3.
+ *  - Ownership: the caller owns every device buffer (inputs, state, the
+ *    workspace); the library owns only host-side objects inside hmc_ctx and a
+ *    few small device tables it allocates at init (freed by hmc_destroy).
+ *    Device pointers are plain HIP device addresses; `stream` is a hipStream_t
+ *    (void* here so that the header needs no HIP include).  All device work is
+ *    stream-ordered on that stream.  Calls that return host scalars
+ *    synchronise the stream before returning.
+ *  - Errors: every call returns hmc_status.  HMC_EINVAL: bad shape, size or
+ *    null pointer; HMC_ENOMEM: workspace too small; HMC_EDEVICE: a HIP call
+ *    failed; HMC_EUNSUPPORTED: a valid request this build does not implement;
+ *    HMC_ENUMERIC: non-finite energy (the trajectory is rejected and the state
+ *    restored).  hmc_last_error() returns a static description.  A context is
+ *    not thread-safe; use one per stream.
+ *  - Random numbers: Philox4x32-10 keyed by `seed`; counter =
+ *    (block, draw index, chain_id << 8 | stream, sub index).  Streams: 3 HMC
+ *    momenta, 4 HMC accept, 5 chi^2, 6 GIG, 7 bias, 8 joint-move momenta,
+ *    9 joint-move accept.
+ */
+#ifndef LIBHMC_HMC_H
+#define LIBHMC_HMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t hmc_status;
+#define HMC_OK 0
+#define HMC_EINVAL (-1)
+#define HMC_ENOMEM (-2)
+#define HMC_EDEVICE (-3)
+#define HMC_EUNSUPPORTED (-4)
+#define HMC_ENUMERIC (-5)
+
+typedef struct hmc_ctx hmc_ctx;
+
+/* Sampler settings for one chain. */
+typedef struct hmc_config {
+  int32_t n;                 /* grid side N */
+  double box;                /* box side L [Mpc/h] */
+  int32_t n_sub;             /* number of galaxy subsamples c (1..32) */
+  int32_t n_bins;            /* number of k-shells (1..128) */
+  double alpha_prior;        /* power-law prior index: P^-alpha (1 = Jeffreys) */
+  uint64_t seed;             /* Philox key */
+  uint32_t chain_id;         /* Philox chain field (< 2^24) */
+  int32_t n_leapfrog;        /* leapfrog steps per trajectory (>= 1) */
+  double eps;                /* leapfrog step size */
+  uint32_t fixed_bias_mask;  /* bit l set: b_l is held at its current value */
+  int32_t rj_move;           /* 1: run the joint (P, delta) move in gibbs_sweep */
+  double rj_log_bound;       /* joint move keeps ln lambda within +-bound of its
+                                value at init (reflecting walls); 0 -> 10 */
+} hmc_config;
+
+/* Caller-owned device buffers of one chain. */
+typedef struct hmc_buffers {
+  const float* R;       /* [c][N][N][N] survey response R^l_i >= 0 */
+  const float* counts;  /* [c][N][N][N] galaxy counts N^l_i (0 where R = 0) */
+  float* delta_k;       /* [N][N][N/2+1] complex64: density state delta_hat */
+  float* mom_k;         /* [N][N][N/2+1] complex64: momentum of the last trajectory */
+  float* grad_k;        /* [N][N][N/2+1] complex64: F(alpha delta - beta) at delta_hat */
+  float* delta_r;       /* [N][N][N] real-space density of the state */
+  float* alpha;         /* [N][N][N] sum_l b_l^2 Nbar_l R^l (library writes) */
+  float* beta;          /* [N][N][N] sum_l b_l (N^l - Nbar_l R^l) (library writes) */
+  void* work;           /* workspace, at least hmc_workspace_bytes(cfg) bytes */
+  size_t work_bytes;
+} hmc_buffers;
+
+/* Per-sweep results; the arrays are library-owned views valid until the next
+ * call on the same context. */
+typedef struct hmc_sweep_stats {
+  double dH;             /* energy error of the density trajectory */
+  int32_t accepted;      /* 1 if the density trajectory was accepted */
+  double rj_dH;          /* energy error of the joint move (0 if off) */
+  int32_t rj_accepted;   /* 1 if the joint move was accepted */
+  const double* pk;      /* [n_bins] P_m after the sweep, (Mpc/h)^3 */
+  const double* bias;    /* [c] */
+  const double* nbar;    /* [c] */
+} hmc_sweep_stats;
+
+/* Workspace bytes one chain needs (0 on invalid config). */
+size_t hmc_workspace_bytes(const hmc_config* cfg);
+
+/* Create a context for one chain.  Validates the configuration, binds the
+ * buffers, computes the data model's static sums and alpha, beta (Sec. "The
+ * density likelihood and the data model"), the shell tables and the mass of
+ * the text after eq. Mass_matrix (diagonal of S^-1 + diag(alpha) in Fourier
+ * space), and the real field and gradient of the initial delta_hat (which the
+ * caller has written to delta_k; zeros are fine).  bias, nbar: [c] host
+ * float64; pk: [n_bins] host float64 (Mpc/h)^3. */
+hmc_status hmc_init(const hmc_config* cfg, const hmc_buffers* buf, const double* bias,
+                    const double* nbar, const double* pk, void* stream, hmc_ctx** out);
+
+/* Same for `n_chains` independent chains that advance together: every stage of
+ * a trajectory or sweep is one launch over all chains.  All chains must use
+ * the same n_leapfrog.  cfg, buf: [n_chains]; bias, nbar: concatenated [sum c];
+ * pk: concatenated [sum n_bins]. */
+hmc_status hmc_init_batch(const hmc_config* cfg, const hmc_buffers* buf, int32_t n_chains,
+                          const double* bias, const double* nbar, const double* pk, void* stream,
+                          hmc_ctx** out);
+
+/* One HMC trajectory for the density (Sec. "The HMC algorithm"): momenta
+ * p ~ N(0, M) drawn as p_hat = sqrt(m_k) F w, KDK leapfrog of eqs. HAMILTON1_a /
+ * HAMILTON2_a with n_leapfrog steps of size eps, Metropolis test of eq.
+ * acceptance_rule (accept iff ln u < -dH).  On reject delta_k, grad_k and
+ * delta_r are restored; mom_k holds the final momentum of the proposal.
+ * dH, accepted: host pointers with one entry per chain. */
+hmc_status leapfrog_trajectory(hmc_ctx* ctx, uint64_t traj_index, double* dH, int32_t* accepted);
+
+/* Energies of eq. Hamiltonian for chain `chain` on the current buffers
+ * (float64 accumulation): out[0] kinetic 1/2 sum_k |p_hat|^2/m_k from mom_k,
+ * out[1] prior 1/2 sum_k |delta_hat|^2/lambda_k from delta_k, out[2] data
+ * sum_i (1/2 alpha_i delta_i^2 - beta_i delta_i) from delta_r (eq.
+ * Wiener_Posterior_psi without constants).  out: host, 3 doubles. */
+hmc_status hamiltonian(hmc_ctx* ctx, int32_t chain, double* out);
+
+/* Shell power of chain `chain`: sigma_m = sum_{k in m} |delta_hat_k|^2 over the
+ * full grid (the sigma_m that follows eq. INVERSE_GAMMA) and mode counts n_m.
+ * sigma: host [n_bins] float64; n_modes: host [n_bins] int64 (may be NULL). */
+hmc_status shell_power(hmc_ctx* ctx, int32_t chain, double* sigma, int64_t* n_modes);
+
+/* One block sweep (eq. multiblock): density HMC, P | delta, the joint move (if
+ * rj_move), Nbar | delta, b, b | delta, Nbar, then alpha, beta, mass and
+ * gradient are refreshed.  out: host [n_chains]. */
+hmc_status gibbs_sweep(hmc_ctx* ctx, uint64_t sweep_index, hmc_sweep_stats* out);
+
+/* Replace the density state of chain `chain` with a real field (device
+ * [N][N][N] float32), e.g. a warm start; the mean is removed. */
+hmc_status hmc_set_state(hmc_ctx* ctx, int32_t chain, const float* delta_r_dev);
+
+/* Replace P (host [n_bins], (Mpc/h)^3), biases and Nbar (host [c]) of a chain;
+ * NULL leaves a block unchanged.  Refreshes alpha, beta, mass and gradient. */
+hmc_status hmc_set_params(hmc_ctx* ctx, int32_t chain, const double* pk, const double* bias,
+                          const double* nbar);
+
+/* Install caller-computed coefficients alpha, beta (device [N][N][N] float32,
+ * the two real fields of eq. Wiener_Posterior_force) for chain `chain`, in
+ * place of the ones the library derives from R, counts, b and Nbar; the mean
+ * of alpha, the mass and the gradient are refreshed from them.  They stay in
+ * force until the next gibbs_sweep or hmc_set_params recomputes them. */
+hmc_status hmc_set_coefficients(hmc_ctx* ctx, int32_t chain, const float* alpha_dev,
+                                const float* beta_dev);
+
+/* Current P, b, Nbar of a chain (host arrays; NULL skips). */
+hmc_status hmc_get_params(hmc_ctx* ctx, int32_t chain, double* pk, double* bias, double* nbar);
+
+/* Shell index of every stored mode of chain `chain` (device [N][N][N/2+1]
+ * int16, -1 for k = 0), as the kernels compute it. */
+hmc_status hmc_shell_index(hmc_ctx* ctx, int32_t chain, int16_t* out_dev);
+
+/* Elementwise diagonal mass in real space (learned mass): with logvar_dev a
+ * device [N][N][N] float32 log-variance v, the inverse mass becomes
+ * D^(1/2) F^-1 diag(1/m_k) F D^(1/2) with D = v / mean(v).  NULL restores the
+ * paper's Fourier-diagonal mass. */
+hmc_status hmc_set_mass(hmc_ctx* ctx, int32_t chain, const float* logvar_dev);
+
+/* Device timing of the leapfrog passes (tracing).  enable = 1 starts
+ * recording HIP events on the context's stream around every launch of the
+ * step passes and clears the totals; enable = 0 stops recording; enable = -1
+ * only reads.  ms[4] / launches[4] (host, may be NULL) receive the summed
+ * durations and launch counts of: [0] k-space passes of interior leapfrog
+ * steps (kick, drift and both x transforms), [1] y passes, [2] real-space
+ * passes (z transforms and the data force), [3] every other pass kernel.
+ * Reading synchronises the stream. */
+hmc_status hmc_timing(hmc_ctx* ctx, int32_t enable, double* ms, int64_t* launches);
+
+/* Static description of the last error on this context (or of the last
+ * context-free failure when ctx is NULL). */
+const char* hmc_last_error(const hmc_ctx* ctx);
+
+void hmc_destroy(hmc_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

@@ -1,0 +1,265 @@
+"""ctypes binding of libhmc (include/hmc.h): argument marshalling only.
+
+Device memory and the stream come from PyTorch; every computation runs in the
+library's HIP kernels.  Importing this module does not load the library;
+``lib()`` does, and raises if the built ``libhmc.so`` is missing.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhmc.so")
+
+HMC_OK = 0
+STATUS = {0: "ok", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EUNSUPPORTED", -5: "ENUMERIC"}
+
+
+class HmcConfig(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("box", ctypes.c_double), ("n_sub", ctypes.c_int32),
+                ("n_bins", ctypes.c_int32), ("alpha_prior", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("chain_id", ctypes.c_uint32),
+                ("n_leapfrog", ctypes.c_int32), ("eps", ctypes.c_double),
+                ("fixed_bias_mask", ctypes.c_uint32), ("rj_move", ctypes.c_int32),
+                ("rj_log_bound", ctypes.c_double)]
+
+
+class HmcBuffers(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_void_p), ("counts", ctypes.c_void_p), ("delta_k", ctypes.c_void_p),
+                ("mom_k", ctypes.c_void_p), ("grad_k", ctypes.c_void_p),
+                ("delta_r", ctypes.c_void_p), ("alpha", ctypes.c_void_p),
+                ("beta", ctypes.c_void_p), ("work", ctypes.c_void_p),
+                ("work_bytes", ctypes.c_size_t)]
+
+
+class HmcSweepStats(ctypes.Structure):
+    _fields_ = [("dH", ctypes.c_double), ("accepted", ctypes.c_int32),
+                ("rj_dH", ctypes.c_double), ("rj_accepted", ctypes.c_int32),
+                ("pk", ctypes.POINTER(ctypes.c_double)),
+                ("bias", ctypes.POINTER(ctypes.c_double)),
+                ("nbar", ctypes.POINTER(ctypes.c_double))]
+
+
+EXPORTS = ["hmc_workspace_bytes", "hmc_init", "hmc_init_batch", "leapfrog_trajectory",
+           "hamiltonian", "shell_power", "gibbs_sweep", "hmc_set_state", "hmc_set_params",
+           "hmc_set_coefficients", "hmc_get_params", "hmc_shell_index", "hmc_set_mass",
+           "hmc_timing", "hmc_last_error", "hmc_destroy"]
+
+_lib = None
+
+
+def lib(path=LIB_PATH):
+    """Load libhmc.so (raises FileNotFoundError when it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(f"{path} is missing: build it with python -m paper_1306_1821_amd.build")
+    L = ctypes.CDLL(path)
+    P, D, I32, U64 = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int32, ctypes.c_uint64
+    L.hmc_workspace_bytes.argtypes = [ctypes.POINTER(HmcConfig)]
+    L.hmc_workspace_bytes.restype = ctypes.c_size_t
+    L.hmc_init.argtypes = [ctypes.POINTER(HmcConfig), ctypes.POINTER(HmcBuffers), D, D, D, P,
+                           ctypes.POINTER(P)]
+    L.hmc_init_batch.argtypes = [ctypes.POINTER(HmcConfig), ctypes.POINTER(HmcBuffers), I32, D, D,
+                                 D, P, ctypes.POINTER(P)]
+    L.leapfrog_trajectory.argtypes = [P, U64, D, ctypes.POINTER(I32)]
+    L.hamiltonian.argtypes = [P, I32, D]
+    L.shell_power.argtypes = [P, I32, D, ctypes.POINTER(ctypes.c_int64)]
+    L.gibbs_sweep.argtypes = [P, U64, ctypes.POINTER(HmcSweepStats)]
+    L.hmc_set_state.argtypes = [P, I32, P]
+    L.hmc_set_params.argtypes = [P, I32, D, D, D]
+    L.hmc_set_coefficients.argtypes = [P, I32, P, P]
+    L.hmc_get_params.argtypes = [P, I32, D, D, D]
+    L.hmc_shell_index.argtypes = [P, I32, P]
+    L.hmc_set_mass.argtypes = [P, I32, P]
+    L.hmc_timing.argtypes = [P, I32, D, ctypes.POINTER(ctypes.c_int64)]
+    L.hmc_last_error.argtypes = [P]
+    L.hmc_last_error.restype = ctypes.c_char_p
+    L.hmc_destroy.argtypes = [P]
+    L.hmc_destroy.restype = None
+    for name in EXPORTS:
+        if name not in ("hmc_workspace_bytes", "hmc_last_error", "hmc_destroy"):
+            getattr(L, name).restype = ctypes.c_int32
+    _lib = L
+    return L
+
+
+class HmcError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _dptr(a):
+    return np.ascontiguousarray(a, dtype=np.float64).ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class Sampler:
+    """One or more chains on one GPU.
+
+    chains: list of dicts with keys n, box, nb, R [c,N,N,N], counts [c,N,N,N]
+    (numpy or torch), bias [c], nbar [c], pk [nb] (Mpc/h)^3, and optional
+    seed, chain_id, nsteps, eps, alpha_prior, fixed_mask, rj, delta_k0
+    (complex [N,N,N/2+1]).
+    """
+
+    def __init__(self, chains, device="cuda:0", stream=None):
+        import torch
+        self.torch = torch
+        self.L = lib()
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.chains = []
+        cfgs = (HmcConfig * len(chains))()
+        bufs = (HmcBuffers * len(chains))()
+        bias, nbar, pk = [], [], []
+        for i, c in enumerate(chains):
+            n, nsub = int(c["n"]), int(np.shape(c["R"])[0])
+            cfg = cfgs[i]
+            cfg.n, cfg.box, cfg.n_sub, cfg.n_bins = n, float(c["box"]), nsub, int(c["nb"])
+            cfg.alpha_prior = float(c.get("alpha_prior", 1.0))
+            cfg.seed = int(c.get("seed", 1))
+            cfg.chain_id = int(c.get("chain_id", i))
+            cfg.n_leapfrog = int(c.get("nsteps", 20))
+            cfg.eps = float(c.get("eps", 0.05))
+            cfg.fixed_bias_mask = int(c.get("fixed_mask", 1))
+            cfg.rj_move = int(bool(c.get("rj", False)))
+            cfg.rj_log_bound = float(c.get("rj_log_bound", 10.0))
+            wb = self.L.hmc_workspace_bytes(ctypes.byref(cfg))
+            if wb == 0:
+                raise HmcError(-1, f"invalid configuration for chain {i}")
+            f32 = dict(dtype=torch.float32, device=self.device)
+            h = n // 2 + 1
+            t = dict(
+                R=torch.as_tensor(np.asarray(c["R"], dtype=np.float32)).to(self.device).contiguous(),
+                counts=torch.as_tensor(np.asarray(c["counts"], dtype=np.float32)).to(self.device).contiguous(),
+                delta_k=torch.zeros((n, n, h), dtype=torch.complex64, device=self.device),
+                mom_k=torch.zeros((n, n, h), dtype=torch.complex64, device=self.device),
+                grad_k=torch.zeros((n, n, h), dtype=torch.complex64, device=self.device),
+                delta_r=torch.zeros((n, n, n), **f32),
+                alpha=torch.zeros((n, n, n), **f32),
+                beta=torch.zeros((n, n, n), **f32),
+                work=torch.zeros(wb, dtype=torch.uint8, device=self.device))
+            if c.get("delta_k0") is not None:
+                t["delta_k"].copy_(torch.as_tensor(np.asarray(c["delta_k0"], dtype=np.complex64)))
+            b = bufs[i]
+            b.R, b.counts = t["R"].data_ptr(), t["counts"].data_ptr()
+            b.delta_k, b.mom_k, b.grad_k = (t["delta_k"].data_ptr(), t["mom_k"].data_ptr(),
+                                           t["grad_k"].data_ptr())
+            b.delta_r, b.alpha, b.beta = t["delta_r"].data_ptr(), t["alpha"].data_ptr(), t["beta"].data_ptr()
+            b.work, b.work_bytes = t["work"].data_ptr(), wb
+            bias += list(np.asarray(c["bias"], dtype=np.float64))
+            nbar += list(np.asarray(c["nbar"], dtype=np.float64))
+            pk += list(np.asarray(c["pk"], dtype=np.float64))
+            self.chains.append(dict(n=n, nb=cfg.n_bins, nsub=nsub, box=cfg.box, t=t))
+        self._cfgs, self._bufs = cfgs, bufs
+        torch.cuda.synchronize(self.device)
+        ctx = ctypes.c_void_p()
+        st = self.L.hmc_init_batch(cfgs, bufs, len(chains), _dptr(bias), _dptr(nbar), _dptr(pk),
+                                   ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx))
+        if st != HMC_OK:
+            raise HmcError(st, self.L.hmc_last_error(None).decode())
+        self.ctx = ctx
+
+    # ------------------------------------------------------------------ helpers
+    def _check(self, st):
+        if st != HMC_OK:
+            raise HmcError(st, self.L.hmc_last_error(self.ctx).decode())
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.L.hmc_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def tensors(self, chain=0):
+        return self.chains[chain]["t"]
+
+    # ------------------------------------------------------------------ API
+    def trajectory(self, traj_index):
+        k = len(self.chains)
+        dH = (ctypes.c_double * k)()
+        acc = (ctypes.c_int32 * k)()
+        self._check(self.L.leapfrog_trajectory(self.ctx, int(traj_index), dH, acc))
+        return np.array(dH[:]), np.array(acc[:], dtype=bool)
+
+    def hamiltonian(self, chain=0):
+        out = (ctypes.c_double * 3)()
+        self._check(self.L.hamiltonian(self.ctx, chain, out))
+        return tuple(out[:])
+
+    def shell_power(self, chain=0):
+        nb = self.chains[chain]["nb"]
+        sig = (ctypes.c_double * nb)()
+        nm = (ctypes.c_int64 * nb)()
+        self._check(self.L.shell_power(self.ctx, chain, sig, nm))
+        return np.array(sig[:]), np.array(nm[:], dtype=np.int64)
+
+    def sweep(self, sweep_index):
+        k = len(self.chains)
+        st = (HmcSweepStats * k)()
+        self._check(self.L.gibbs_sweep(self.ctx, int(sweep_index), st))
+        out = []
+        for i, c in enumerate(self.chains):
+            s = st[i]
+            out.append(dict(dH=s.dH, accepted=bool(s.accepted), rj_dH=s.rj_dH,
+                            rj_accepted=bool(s.rj_accepted),
+                            pk=np.array(s.pk[:c["nb"]]), bias=np.array(s.bias[:c["nsub"]]),
+                            nbar=np.array(s.nbar[:c["nsub"]])))
+        return out
+
+    def set_state(self, chain, delta_r):
+        x = self.torch.as_tensor(np.asarray(delta_r, dtype=np.float32)).to(self.device).contiguous()
+        self._check(self.L.hmc_set_state(self.ctx, chain, ctypes.c_void_p(x.data_ptr())))
+        self.torch.cuda.synchronize(self.device)
+
+    def set_params(self, chain, pk=None, bias=None, nbar=None):
+        f = lambda a: None if a is None else _dptr(a)
+        self._check(self.L.hmc_set_params(self.ctx, chain, f(pk), f(bias), f(nbar)))
+
+    def set_coefficients(self, chain, alpha, beta):
+        a = self.torch.as_tensor(np.asarray(alpha, dtype=np.float32)).to(self.device).contiguous()
+        b = self.torch.as_tensor(np.asarray(beta, dtype=np.float32)).to(self.device).contiguous()
+        self._check(self.L.hmc_set_coefficients(self.ctx, chain, ctypes.c_void_p(a.data_ptr()),
+                                                ctypes.c_void_p(b.data_ptr())))
+        self.torch.cuda.synchronize(self.device)
+
+    def get_params(self, chain=0):
+        c = self.chains[chain]
+        pk = np.zeros(c["nb"])
+        b = np.zeros(c["nsub"])
+        nb = np.zeros(c["nsub"])
+        self._check(self.L.hmc_get_params(self.ctx, chain, _dptr_out(pk), _dptr_out(b), _dptr_out(nb)))
+        return pk, b, nb
+
+    def shell_index(self, chain=0):
+        n = self.chains[chain]["n"]
+        out = self.torch.empty((n, n, n // 2 + 1), dtype=self.torch.int16, device=self.device)
+        self._check(self.L.hmc_shell_index(self.ctx, chain, ctypes.c_void_p(out.data_ptr())))
+        return out.cpu().numpy()
+
+    def timing(self, enable=-1):
+        """Summed device milliseconds and launch counts of the step passes
+        ([0] interior k-space passes, [1] y passes, [2] real-space passes, [3] other)."""
+        ms = (ctypes.c_double * 4)()
+        n = (ctypes.c_int64 * 4)()
+        self._check(self.L.hmc_timing(self.ctx, int(enable), ms, n))
+        return np.array(ms[:]), np.array(n[:], dtype=np.int64)
+
+    def state(self, chain=0):
+        """Host copies of delta_k, mom_k, grad_k, delta_r, alpha, beta."""
+        self.torch.cuda.synchronize(self.device)
+        t = self.chains[chain]["t"]
+        return {k: t[k].cpu().numpy() for k in ("delta_k", "mom_k", "grad_k", "delta_r", "alpha", "beta")}
+
+
+def _dptr_out(a):
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))

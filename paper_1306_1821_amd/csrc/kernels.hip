@@ -1,0 +1,1104 @@
+// HIP kernels for the HMC density sampler (gfx950).
+//
+// One leapfrog step (kick-drift-kick, Sec. "The HMC algorithm") is four
+// in-place passes over one intermediate half-complex grid T:
+//   x-pass  (k space): forward x-FFT of the incoming gradient partial transform,
+//           kick p_hat -= eps' (delta_hat / lambda_k + g_hat) (eq. HAMILTON2_a),
+//           drift delta_hat += eps p_hat / m_k (eq. HAMILTON1_a), inverse x-FFT
+//           of delta_hat -> T;
+//   y-pass  inverse y-FFT;
+//   z-pass  (real space): C2R along z gives delta, g = alpha delta - beta (the
+//           data force of eq. Wiener_Posterior_force), R2C along z;
+//   y-pass  forward y-FFT.
+// alpha_i = sum_l b_l^2 Nbar_l R^l_i and beta_i = sum_l b_l (N^l_i - Nbar_l R^l_i)
+// are precomputed once per sweep.  The unitary normalisation N^(-3/2) is
+// applied in the x-pass (both directions).
+#include "kernels.hpp"
+#include "fft.hpp"
+#include "rng.hpp"
+#include "samplers.hpp"
+
+namespace hmc {
+using namespace hmcfft;
+
+// ------------------------------------------------------------------ configs
+// strided C2C passes (x and y): T threads per pencil, B pencils per block
+template <int N> struct XC;
+template <> struct XC<8>   { static constexpr int T = 2,  B = 128; using RL = Radices<4, 2>; };
+template <> struct XC<16>  { static constexpr int T = 4,  B = 64;  using RL = Radices<4, 4>; };
+template <> struct XC<32>  { static constexpr int T = 4,  B = 64;  using RL = Radices<8, 4>; };
+template <> struct XC<64>  { static constexpr int T = 8,  B = 32;  using RL = Radices<8, 8>; };
+template <> struct XC<128> { static constexpr int T = 8,  B = 32;  using RL = Radices<16, 8>; };
+template <> struct XC<192> { static constexpr int T = 16, B = 16;  using RL = Radices<4, 4, 12>; };
+template <> struct XC<256> { static constexpr int T = 16, B = 16;  using RL = Radices<16, 16>; };
+// z pass: half-length complex transform of M = N/2 points per row
+template <int N> struct ZC;
+template <> struct ZC<8>   { static constexpr int T = 1, B = 256; using RL = Radices<4>; };
+template <> struct ZC<16>  { static constexpr int T = 2, B = 128; using RL = Radices<4, 2>; };
+template <> struct ZC<32>  { static constexpr int T = 4, B = 64;  using RL = Radices<4, 4>; };
+template <> struct ZC<64>  { static constexpr int T = 4, B = 64;  using RL = Radices<8, 4>; };
+template <> struct ZC<128> { static constexpr int T = 8, B = 32;  using RL = Radices<8, 8>; };
+template <> struct ZC<192> { static constexpr int T = 8, B = 32;  using RL = Radices<4, 4, 6>; };
+template <> struct ZC<256> { static constexpr int T = 8, B = 32;  using RL = Radices<16, 8>; };
+
+template <int N> constexpr int xlds() { return N * (XC<N>::B + 1) * 8; }
+template <int N> constexpr int zlds() { return ZC<N>::B * (N / 2 + 2) * 8; }
+
+#define HMC_FOR_N(X) X(8) X(16) X(32) X(64) X(128) X(192) X(256)
+
+bool supported_n(int n) {
+  return n == 8 || n == 16 || n == 32 || n == 64 || n == 128 || n == 192 || n == 256;
+}
+int xpass_lds_bytes(int n) {
+#define C(NN) if (n == NN) return xlds<NN>();
+  HMC_FOR_N(C)
+#undef C
+  return 0;
+}
+int zpass_lds_bytes(int n) {
+#define C(NN) if (n == NN) return zlds<NN>();
+  HMC_FOR_N(C)
+#undef C
+  return 0;
+}
+int xpass_tiles(int n) {
+#define C(NN) if (n == NN) return (NN * (NN / 2 + 1) + XC<NN>::B - 1) / XC<NN>::B;
+  HMC_FOR_N(C)
+#undef C
+  return 0;
+}
+int zpass_tiles(int n) {
+#define C(NN) if (n == NN) return (NN * NN + ZC<NN>::B - 1) / ZC<NN>::B;
+  HMC_FOR_N(C)
+#undef C
+  return 0;
+}
+
+// ------------------------------------------------------------------ helpers
+__device__ __forceinline__ int find_chain(const ChainDev* ch, int nch, int tile, int cls) {
+  int c = 0;
+  while (c + 1 < nch && tile >= ch[c + 1].tb[cls]) ++c;
+  return c;
+}
+
+__device__ __forceinline__ int sfreq(int k, int n) { return k <= n / 2 ? k : k - n; }
+
+// Shell of a mode with signed integer frequencies: the m with
+// m^2 q_max < nb^2 q <= (m+1)^2 q_max, q_max = 3 (n/2)^2; -1 for q = 0.
+__device__ __forceinline__ int shell_of(int fx, int fy, int fz, int n, int nb) {
+  const uint64_t q = (uint64_t)(fx * fx + fy * fy + fz * fz);
+  if (q == 0) return -1;
+  const uint64_t qmax = 3ull * (uint64_t)(n / 2) * (uint64_t)(n / 2);
+  const uint64_t lhs = (uint64_t)nb * (uint64_t)nb * q;
+  int t = (int)ceilf(sqrtf((float)lhs / (float)qmax));
+  if (t < 1) t = 1;
+  while ((uint64_t)t * (uint64_t)t * qmax < lhs) ++t;
+  while (t > 1 && (uint64_t)(t - 1) * (uint64_t)(t - 1) * qmax >= lhs) --t;
+  return t - 1;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// Deterministic block sum (fixed butterfly tree per wave, fixed wave order).
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  return red[0] + red[1] + red[2] + red[3];
+}
+
+// per-wave shell bins in LDS: bins[wave * kMaxBins + m]
+__device__ __forceinline__ void bins_zero(double* bins) {
+  for (int i = threadIdx.x; i < 4 * kMaxBins; i += kThreads) bins[i] = 0.0;
+  __syncthreads();
+}
+__device__ __forceinline__ void bins_flush(double* bins, double* dst, int nb) {
+  __syncthreads();
+  for (int m = threadIdx.x; m < nb; m += kThreads)
+    dst[m] = ((bins[m] + bins[kMaxBins + m]) + bins[2 * kMaxBins + m]) + bins[3 * kMaxBins + m];
+  __syncthreads();
+}
+
+// ------------------------------------------------------------------ x pass
+template <int N, int MODE>
+__device__ __forceinline__ void xpass(const ChainDev& d, int lt, const XArgs a, const float2* __restrict__ twall,
+                      float2* lds, double* red, double* bins) {
+  using C = XC<N>;
+  constexpr int T = C::T, B = C::B, E = N / T, H = N / 2 + 1, ES = B + 1;
+  const float2* tw = twall + tw_offset(N);
+  const int tid = threadIdx.x, b = tid % B, t = tid / B;
+  const int col = lt * B + b;
+  const bool active = col < N * H;
+  const size_t stride = (size_t)N * H;
+  const int ky = active ? col / H : 0, kz = active ? col % H : 0;
+  const int fy = sfreq(ky, N);
+  const double wz = (kz == 0 || kz == N / 2) ? 1.0 : 2.0;
+  const float norm = d.norm;
+  const float kick = a.kick * d.eps, drift = a.drift * d.eps;
+  float2* L = lds + b;
+  float2 v[E];
+
+  const bool dot = (MODE == X_FWD) && (a.flags & XF_DOT);
+  if (dot) bins_zero(bins);
+
+  if constexpr (MODE != X_INV) {
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      v[e] = active ? d.T[(size_t)(t + T * e) * stride + col] : make_float2(0.f, 0.f);
+    fft<N, T, +1>(v, L, ES, t, active, tw, typename C::RL{});
+  }
+
+  double acc0 = 0.0, acc1 = 0.0;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int kx = t + T * e;
+    const int m = shell_of(sfreq(kx, N), fy, kz, N, d.nb);
+    const size_t idx = (size_t)kx * stride + col;
+    if constexpr (MODE == X_INV) {
+      float2 x = active ? d.dk[idx] : make_float2(0.f, 0.f);
+      float s = norm;
+      if ((a.flags & XF_SCALE) && m >= 0) s *= d.tf[kTScale + m];
+      v[e] = m < 0 ? make_float2(0.f, 0.f) : cscale(x, s);
+    } else if constexpr (MODE == X_FWD) {
+      float2 g = m < 0 ? make_float2(0.f, 0.f) : cscale(v[e], norm);
+      if (active && !(a.flags & XF_NOSTORE)) {
+        float2* out = (a.flags & XF_OUT_DK) ? d.dk : (a.flags & XF_OUT_ALT) ? d.bgk : d.gk;
+        out[idx] = g;
+      }
+      if (dot && active && m >= 0) {
+        float2 x = d.dk[idx];
+        const float s = (a.flags & XF_SCALE) ? d.tf[kTScale + m] : 1.f;
+        const double val = wz * ((double)(s * x.x) * g.x + (double)(s * x.y) * g.y);
+        atomicAdd(&bins[(threadIdx.x >> 6) * kMaxBins + m], val);
+      }
+    } else {
+      // X_START, X_STEP, X_END: kick (and drift)
+      float2 dk = make_float2(0.f, 0.f), pk = make_float2(0.f, 0.f), g;
+      if (active) dk = d.dk[idx];
+      if constexpr (MODE == X_START) {
+        // fresh momentum p_hat = sqrt(m_k) F w; gradient of the current state from memory
+        const float sq = m >= 0 ? d.tf[kTSqrtMass + m] : 0.f;
+        pk = cscale(v[e], norm * sq);
+        g = active ? d.gk[idx] : make_float2(0.f, 0.f);
+        if (active) {
+          d.bdk[idx] = dk;
+          d.bgk[idx] = g;
+        }
+        if (active && m >= 0) {
+          acc0 += wz * ((double)pk.x * pk.x + (double)pk.y * pk.y) * d.td[kDInvMass + m];
+          acc1 += wz * ((double)dk.x * dk.x + (double)dk.y * dk.y) * d.td[kDInvLam + m];
+        }
+      } else {
+        g = cscale(v[e], norm);
+        if (active) pk = d.pk[idx];
+      }
+      if (m >= 0) {
+        const float il = d.tf[kTInvLam + m];
+        pk.x -= kick * (dk.x * il + g.x);
+        pk.y -= kick * (dk.y * il + g.y);
+        if constexpr (MODE != X_END) {
+          const float im = d.tf[kTInvMass + m];
+          dk.x += drift * pk.x * im;
+          dk.y += drift * pk.y * im;
+        }
+      } else {
+        pk = make_float2(0.f, 0.f);
+        dk = make_float2(0.f, 0.f);
+      }
+      if constexpr (MODE == X_END) {
+        if (active && m >= 0) {
+          acc0 += wz * ((double)pk.x * pk.x + (double)pk.y * pk.y) * d.td[kDInvMass + m];
+          acc1 += wz * ((double)dk.x * dk.x + (double)dk.y * dk.y) * d.td[kDInvLam + m];
+        }
+        if (active) {
+          d.pk[idx] = pk;
+          d.gk[idx] = m < 0 ? make_float2(0.f, 0.f) : g;
+        }
+      } else {
+        if (active) {
+          d.dk[idx] = dk;
+          d.pk[idx] = pk;
+        }
+        v[e] = cscale(dk, norm);
+      }
+    }
+  }
+
+  if constexpr (MODE == X_INV || MODE == X_START || MODE == X_STEP) {
+    fft<N, T, -1>(v, L, ES, t, active, tw, typename C::RL{});
+    if (active) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) d.T[(size_t)(t + T * e) * stride + col] = v[e];
+    }
+  }
+  if constexpr (MODE == X_START || MODE == X_END) {
+    const double s0 = block_sum(0.5 * acc0, red);
+    const double s1 = block_sum(0.5 * acc1, red);
+    if (threadIdx.x == 0) {
+      d.part[kPartKin * d.maxtiles + lt] = s0;
+      d.part[kPartPri * d.maxtiles + lt] = s1;
+    }
+  }
+  if (dot) bins_flush(bins, d.shpart + (size_t)lt * d.nb, d.nb);
+  __syncthreads();
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(kThreads) k_xpass(const ChainDev* __restrict__ ch, int nch,
+                                                     int total, XArgs a,
+                                                     const float2* __restrict__ tw) {
+  extern __shared__ float2 lds[];
+  __shared__ double red[4];
+  __shared__ double bins[4 * kMaxBins];
+  for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
+    const int c = find_chain(ch, nch, tile, kTileXY);
+    const ChainDev& d = ch[c];
+    const int lt = tile - d.tb[kTileXY];
+    switch (d.n) {
+#define C(NN) case NN: xpass<NN, MODE>(d, lt, a, tw, lds, red, bins); break;
+      HMC_FOR_N(C)
+#undef C
+      default: break;
+    }
+  }
+}
+
+// single-size variant: every chain of the launch has this N (lower register use)
+template <int N, int MODE>
+__global__ void __launch_bounds__(kThreads) k_xpass_n(const ChainDev* __restrict__ ch, int nch,
+                                                       int total, XArgs a,
+                                                       const float2* __restrict__ tw) {
+  extern __shared__ float2 lds[];
+  __shared__ double red[4];
+  __shared__ double bins[4 * kMaxBins];
+  for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
+    const int c = find_chain(ch, nch, tile, kTileXY);
+    const ChainDev& d = ch[c];
+    xpass<N, MODE>(d, tile - d.tb[kTileXY], a, tw, lds, red, bins);
+  }
+}
+
+// ------------------------------------------------------------------ y pass
+template <int N, int DIR>
+__device__ __forceinline__ void ypass(const ChainDev& d, int lt, const float2* __restrict__ twall, float2* lds) {
+  using C = XC<N>;
+  constexpr int T = C::T, B = C::B, E = N / T, H = N / 2 + 1, ES = B + 1;
+  const float2* tw = twall + tw_offset(N);
+  const int tid = threadIdx.x, b = tid % B, t = tid / B;
+  const int p = lt * B + b;
+  const bool active = p < N * H;
+  const int x = active ? p / H : 0, kz = active ? p % H : 0;
+  float2* base = d.T + (size_t)x * N * H + kz;
+  float2 v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = active ? base[(size_t)(t + T * e) * H] : make_float2(0.f, 0.f);
+  fft<N, T, DIR>(v, lds + b, ES, t, active, tw, typename C::RL{});
+  if (active) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) base[(size_t)(t + T * e) * H] = v[e];
+  }
+}
+
+template <int DIR>
+__global__ void __launch_bounds__(kThreads) k_ypass(const ChainDev* __restrict__ ch, int nch,
+                                                     int total, const float2* __restrict__ tw) {
+  extern __shared__ float2 lds[];
+  for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
+    const int c = find_chain(ch, nch, tile, kTileXY);
+    const ChainDev& d = ch[c];
+    const int lt = tile - d.tb[kTileXY];
+    switch (d.n) {
+#define C(NN) case NN: ypass<NN, DIR>(d, lt, tw, lds); break;
+      HMC_FOR_N(C)
+#undef C
+      default: break;
+    }
+  }
+}
+
+template <int N, int DIR>
+__global__ void __launch_bounds__(kThreads) k_ypass_n(const ChainDev* __restrict__ ch, int nch,
+                                                       int total, const float2* __restrict__ tw) {
+  extern __shared__ float2 lds[];
+  for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
+    const int c = find_chain(ch, nch, tile, kTileXY);
+    const ChainDev& d = ch[c];
+    ypass<N, DIR>(d, tile - d.tb[kTileXY], tw, lds);
+  }
+}
+
+// ------------------------------------------------------------------ z pass
+template <int N, int MODE>
+__device__ __forceinline__ void zpass(const ChainDev& d, int lt, const ZArgs a, const float2* __restrict__ twall,
+                      float2* lds, double* red) {
+  using C = ZC<N>;
+  constexpr int M = N / 2, T = C::T, B = C::B, E = M / T, H = M + 1, RS = M + 2;
+  const float2* twM = twall + tw_offset(M);
+  const float2* twN = twall + tw_offset(N);
+  const int tid = threadIdx.x, t = tid % T, b = tid / T;
+  const int row = lt * B + b;
+  const bool active = row < N * N;
+  float2* L = lds + b * RS;
+  float2* X = d.T + (size_t)(active ? row : 0) * H;
+  const size_t rbase = (size_t)(active ? row : 0) * N;
+  float2 v[E];
+  double dat = 0.0;
+
+  if constexpr (MODE == Z_GRAD || MODE == Z_C2R) {
+    for (int k = t; k <= M; k += T) L[k] = active ? X[k] : make_float2(0.f, 0.f);
+    __syncthreads();
+    // Z_k = (X_k + conj X_{M-k}) + i W_N^-k (X_k - conj X_{M-k}); imaginary parts of
+    // the self-conjugate X_0 and X_M are dropped.
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int k = t + T * e;
+      float2 xa = L[k], xb = cconj(L[M - k]);
+      if (k == 0) {
+        xa = make_float2(L[0].x, 0.f);
+        xb = make_float2(L[M].x, 0.f);
+      }
+      const float2 s = cadd(xa, xb);
+      const float2 r = cmul(cconj(twN[k]), csub(xa, xb));
+      v[e] = make_float2(s.x - r.y, s.y + r.x);
+    }
+    __syncthreads();
+    fft<M, T, -1>(v, L, 1, t, active, twM, typename C::RL{});
+  } else if constexpr (MODE == Z_R2C) {
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      v[e] = active ? reinterpret_cast<const float2*>(a.src + rbase)[t + T * e]
+                    : make_float2(0.f, 0.f);
+  } else {  // Z_NOISE: white noise w_i from Philox stream 3, element = voxel index
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const uint64_t vox = rbase + 2 * (uint64_t)(t + T * e);
+      const hmcrng::U4 w = hmcrng::block(d.seed, d.chain, hmcrng::kMomenta, a.draw, 0,
+                                         (uint32_t)(vox >> 2));
+      double z0, z1;
+      if (((vox >> 1) & 1) == 0)
+        hmcrng::box_muller(w.w[0], w.w[1], &z0, &z1);
+      else
+        hmcrng::box_muller(w.w[2], w.w[3], &z0, &z1);
+      v[e] = make_float2((float)z0, (float)z1);
+    }
+  }
+
+  if constexpr (MODE == Z_GRAD || MODE == Z_C2R) {
+    float* drout = (a.flags & ZF_WRITE_DRN) ? d.drn : (a.flags & ZF_WRITE_DR) ? d.dr : nullptr;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int n = t + T * e;
+      const float2 x = v[e];
+      if (active && drout) reinterpret_cast<float2*>(drout + rbase)[n] = x;
+      if (MODE == Z_GRAD || (a.flags & ZF_DATA)) {
+        const float2 al = active ? reinterpret_cast<const float2*>(d.alpha + rbase)[n]
+                                 : make_float2(0.f, 0.f);
+        const float2 be = active ? reinterpret_cast<const float2*>(d.beta + rbase)[n]
+                                 : make_float2(0.f, 0.f);
+        if (active && (a.flags & ZF_DATA))
+          dat += (0.5 * al.x * x.x - be.x) * (double)x.x + (0.5 * al.y * x.y - be.y) * (double)x.y;
+        v[e] = make_float2(al.x * x.x - be.x, al.y * x.y - be.y);
+      }
+    }
+  }
+
+  if constexpr (MODE != Z_C2R) {
+    fft<M, T, +1>(v, L, 1, t, active, twM, typename C::RL{});
+    if (active) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) L[t + T * e] = v[e];
+    }
+    __syncthreads();
+    // X_k = E_k + W_N^k O_k, E_k = (Z_k + conj Z_{M-k})/2, O_k = -i (Z_k - conj Z_{M-k})/2
+    if (active) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int k = t + T * e;
+        const float2 zk = L[k];
+        const float2 zc = cconj(L[k == 0 ? 0 : M - k]);
+        const float2 ev = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y + zc.y));
+        const float2 df = csub(zk, zc);
+        const float2 od = make_float2(0.5f * df.y, -0.5f * df.x);
+        X[k] = cadd(ev, cmul(twN[k], od));
+      }
+      if (t == 0) X[M] = make_float2(L[0].x - L[0].y, 0.f);
+    }
+  }
+  if (a.flags & ZF_DATA) {
+    const double s = block_sum(dat, red);
+    if (threadIdx.x == 0) d.part[kPartDat * d.maxtiles + lt] = s;
+  }
+  __syncthreads();
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(kThreads) k_zpass(const ChainDev* __restrict__ ch, int nch,
+                                                     int total, ZArgs a,
+                                                     const float2* __restrict__ tw) {
+  extern __shared__ float2 lds[];
+  __shared__ double red[4];
+  for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
+    const int c = find_chain(ch, nch, tile, kTileZ);
+    const ChainDev& d = ch[c];
+    const int lt = tile - d.tb[kTileZ];
+    switch (d.n) {
+#define C(NN) case NN: zpass<NN, MODE>(d, lt, a, tw, lds, red); break;
+      HMC_FOR_N(C)
+#undef C
+      default: break;
+    }
+  }
+}
+
+template <int N, int MODE>
+__global__ void __launch_bounds__(kThreads) k_zpass_n(const ChainDev* __restrict__ ch, int nch,
+                                                       int total, ZArgs a,
+                                                       const float2* __restrict__ tw) {
+  extern __shared__ float2 lds[];
+  __shared__ double red[4];
+  for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
+    const int c = find_chain(ch, nch, tile, kTileZ);
+    const ChainDev& d = ch[c];
+    zpass<N, MODE>(d, tile - d.tb[kTileZ], a, tw, lds, red);
+  }
+}
+
+// ------------------------------------------------------------------ launches
+static inline int grid_of(int total, int cap) { return total < cap || cap <= 0 ? total : cap; }
+
+template <int N>
+static void launch_x_n(int mode, dim3 g, dim3 bl, int lds, hipStream_t s, const ChainDev* ch,
+                       int nch, int total, XArgs a, const float2* tw) {
+  switch (mode) {
+    case X_INV: hipLaunchKernelGGL((k_xpass_n<N, X_INV>), g, bl, lds, s, ch, nch, total, a, tw); break;
+    case X_FWD: hipLaunchKernelGGL((k_xpass_n<N, X_FWD>), g, bl, lds, s, ch, nch, total, a, tw); break;
+    case X_START: hipLaunchKernelGGL((k_xpass_n<N, X_START>), g, bl, lds, s, ch, nch, total, a, tw); break;
+    case X_STEP: hipLaunchKernelGGL((k_xpass_n<N, X_STEP>), g, bl, lds, s, ch, nch, total, a, tw); break;
+    case X_END: hipLaunchKernelGGL((k_xpass_n<N, X_END>), g, bl, lds, s, ch, nch, total, a, tw); break;
+  }
+}
+template <int N>
+static void launch_z_n(int mode, dim3 g, dim3 bl, int lds, hipStream_t s, const ChainDev* ch,
+                       int nch, int total, ZArgs a, const float2* tw) {
+  switch (mode) {
+    case Z_GRAD: hipLaunchKernelGGL((k_zpass_n<N, Z_GRAD>), g, bl, lds, s, ch, nch, total, a, tw); break;
+    case Z_NOISE: hipLaunchKernelGGL((k_zpass_n<N, Z_NOISE>), g, bl, lds, s, ch, nch, total, a, tw); break;
+    case Z_C2R: hipLaunchKernelGGL((k_zpass_n<N, Z_C2R>), g, bl, lds, s, ch, nch, total, a, tw); break;
+    case Z_R2C: hipLaunchKernelGGL((k_zpass_n<N, Z_R2C>), g, bl, lds, s, ch, nch, total, a, tw); break;
+  }
+}
+
+// uniform_n > 0: every chain of the launch has that N (single-size kernels);
+// otherwise the mixed-size kernels dispatch per tile.
+void launch_xpass(int mode, const ChainDev* ch, int nch, int total, int lds, XArgs a,
+                  const float2* tw, int cap, hipStream_t s, int uniform_n) {
+  dim3 g(grid_of(total, cap)), bl(kThreads);
+  switch (uniform_n) {
+#define C(NN) case NN: launch_x_n<NN>(mode, g, bl, lds, s, ch, nch, total, a, tw); return;
+    HMC_FOR_N(C)
+#undef C
+    default: break;
+  }
+  switch (mode) {
+    case X_INV: hipLaunchKernelGGL(k_xpass<X_INV>, g, bl, lds, s, ch, nch, total, a, tw); break;
+    case X_FWD: hipLaunchKernelGGL(k_xpass<X_FWD>, g, bl, lds, s, ch, nch, total, a, tw); break;
+    case X_START: hipLaunchKernelGGL(k_xpass<X_START>, g, bl, lds, s, ch, nch, total, a, tw); break;
+    case X_STEP: hipLaunchKernelGGL(k_xpass<X_STEP>, g, bl, lds, s, ch, nch, total, a, tw); break;
+    case X_END: hipLaunchKernelGGL(k_xpass<X_END>, g, bl, lds, s, ch, nch, total, a, tw); break;
+  }
+}
+void launch_ypass(int dir, const ChainDev* ch, int nch, int total, int lds, const float2* tw,
+                  int cap, hipStream_t s, int uniform_n) {
+  dim3 g(grid_of(total, cap)), bl(kThreads);
+  switch (uniform_n) {
+#define C(NN)                                                                          \
+  case NN:                                                                             \
+    if (dir > 0)                                                                       \
+      hipLaunchKernelGGL((k_ypass_n<NN, 1>), g, bl, lds, s, ch, nch, total, tw);       \
+    else                                                                               \
+      hipLaunchKernelGGL((k_ypass_n<NN, -1>), g, bl, lds, s, ch, nch, total, tw);      \
+    return;
+    HMC_FOR_N(C)
+#undef C
+    default: break;
+  }
+  if (dir > 0)
+    hipLaunchKernelGGL(k_ypass<1>, g, bl, lds, s, ch, nch, total, tw);
+  else
+    hipLaunchKernelGGL(k_ypass<-1>, g, bl, lds, s, ch, nch, total, tw);
+}
+void launch_zpass(int mode, const ChainDev* ch, int nch, int total, int lds, ZArgs a,
+                  const float2* tw, int cap, hipStream_t s, int uniform_n) {
+  dim3 g(grid_of(total, cap)), bl(kThreads);
+  switch (uniform_n) {
+#define C(NN) case NN: launch_z_n<NN>(mode, g, bl, lds, s, ch, nch, total, a, tw); return;
+    HMC_FOR_N(C)
+#undef C
+    default: break;
+  }
+  switch (mode) {
+    case Z_GRAD: hipLaunchKernelGGL(k_zpass<Z_GRAD>, g, bl, lds, s, ch, nch, total, a, tw); break;
+    case Z_NOISE: hipLaunchKernelGGL(k_zpass<Z_NOISE>, g, bl, lds, s, ch, nch, total, a, tw); break;
+    case Z_C2R: hipLaunchKernelGGL(k_zpass<Z_C2R>, g, bl, lds, s, ch, nch, total, a, tw); break;
+    case Z_R2C: hipLaunchKernelGGL(k_zpass<Z_R2C>, g, bl, lds, s, ch, nch, total, a, tw); break;
+  }
+}
+
+// ------------------------------------------------------------------ elementwise
+// Real-space tiles cover kElemPerTile voxels; k-space tiles kElemPerTile modes.
+
+// alpha, beta from R, counts, bias, Nbar (voxels with R > 0 only); partial sum of alpha.
+__global__ void __launch_bounds__(kThreads) k_coeff(const ChainDev* __restrict__ ch, int nch,
+                                                     int total) {
+  __shared__ double red[4];
+  for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
+    const ChainDev& d = ch[find_chain(ch, nch, tile, kTileR)];
+    const int lt = tile - d.tb[kTileR];
+    double acc = 0.0;
+    for (int j = threadIdx.x; j < kElemPerTile; j += kThreads) {
+      const long long i = (long long)lt * kElemPerTile + j;
+      if (i >= d.nv) break;
+      float al = 0.f, be = 0.f;
+      for (int l = 0; l < d.nsub; ++l) {
+        const float r = d.R[(size_t)l * d.nv + i];
+        if (r > 0.f) {
+          const float bl = (float)d.P[kBias + l], nb = (float)d.P[kNbar + l];
+          al += bl * bl * nb * r;
+          be += bl * (d.counts[(size_t)l * d.nv + i] - nb * r);
+        }
+      }
+      d.alpha[i] = al;
+      d.beta[i] = be;
+      acc += al;
+    }
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) d.part[kPartAlpha * d.maxtiles + lt] = s;
+    __syncthreads();
+  }
+}
+
+// sum of alpha per tile (caller-installed coefficients)
+__global__ void __launch_bounds__(kThreads) k_alpha_sum(const ChainDev* __restrict__ ch, int nch,
+                                                         int total) {
+  __shared__ double red[4];
+  for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
+    const ChainDev& d = ch[find_chain(ch, nch, tile, kTileR)];
+    const int lt = tile - d.tb[kTileR];
+    double acc = 0.0;
+    for (int j = threadIdx.x; j < kElemPerTile; j += kThreads) {
+      const long long i = (long long)lt * kElemPerTile + j;
+      if (i >= d.nv) break;
+      acc += d.alpha[i];
+    }
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) d.part[kPartAlpha * d.maxtiles + lt] = s;
+    __syncthreads();
+  }
+}
+
+// S0 = sum R, B = sum N^2/R, N_obs per subsample (R > 0): mpart[tile][3 l + {0,1,2}]
+__global__ void __launch_bounds__(kThreads) k_static_moments(const ChainDev* __restrict__ ch,
+                                                              int nch, int total) {
+  __shared__ double red[4];
+  for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
+    const ChainDev& d = ch[find_chain(ch, nch, tile, kTileR)];
+    const int lt = tile - d.tb[kTileR];
+    for (int l = 0; l < d.nsub; ++l) {
+      double s0 = 0.0, sb = 0.0, so = 0.0;
+      for (int j = threadIdx.x; j < kElemPerTile; j += kThreads) {
+        const long long i = (long long)lt * kElemPerTile + j;
+        if (i >= d.nv) break;
+        const float r = d.R[(size_t)l * d.nv + i];
+        if (r > 0.f) {
+          const double c = d.counts[(size_t)l * d.nv + i];
+          s0 += r;
+          sb += c * c / (double)r;
+          so += 1.0;
+        }
+      }
+      s0 = block_sum(s0, red);
+      sb = block_sum(sb, red);
+      so = block_sum(so, red);
+      if (threadIdx.x == 0) {
+        double* o = d.mpart + (size_t)lt * 3 * d.nsub + 3 * l;
+        o[0] = s0;
+        o[1] = sb;
+        o[2] = so;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// S1 = sum R delta, S2 = sum R delta^2, T = sum N delta per subsample (R > 0)
+__global__ void __launch_bounds__(kThreads) k_moments(const ChainDev* __restrict__ ch, int nch,
+                                                       int total) {
+  __shared__ double red[4];
+  for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
+    const ChainDev& d = ch[find_chain(ch, nch, tile, kTileR)];
+    const int lt = tile - d.tb[kTileR];
+    for (int l = 0; l < d.nsub; ++l) {
+      double s1 = 0.0, s2 = 0.0, st = 0.0;
+      for (int j = threadIdx.x; j < kElemPerTile; j += kThreads) {
+        const long long i = (long long)lt * kElemPerTile + j;
+        if (i >= d.nv) break;
+        const float r = d.R[(size_t)l * d.nv + i];
+        if (r > 0.f) {
+          const double x = d.dr[i];
+          s1 += (double)r * x;
+          s2 += (double)r * x * x;
+          st += (double)d.counts[(size_t)l * d.nv + i] * x;
+        }
+      }
+      s1 = block_sum(s1, red);
+      s2 = block_sum(s2, red);
+      st = block_sum(st, red);
+      if (threadIdx.x == 0) {
+        double* o = d.mpart + (size_t)lt * 3 * d.nsub + 3 * l;
+        o[0] = s1;
+        o[1] = s2;
+        o[2] = st;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// data energy on delta_r
+__global__ void __launch_bounds__(kThreads) k_energy_r(const ChainDev* __restrict__ ch, int nch,
+                                                        int total) {
+  __shared__ double red[4];
+  for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
+    const ChainDev& d = ch[find_chain(ch, nch, tile, kTileR)];
+    const int lt = tile - d.tb[kTileR];
+    double acc = 0.0;
+    for (int j = threadIdx.x; j < kElemPerTile; j += kThreads) {
+      const long long i = (long long)lt * kElemPerTile + j;
+      if (i >= d.nv) break;
+      const double x = d.dr[i];
+      acc += (0.5 * d.alpha[i] * x - d.beta[i]) * x;
+    }
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) d.part[kPartDat * d.maxtiles + lt] = s;
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ void kindex(long long i, int n, int* fx, int* fy, int* kz) {
+  const int h = n / 2 + 1;
+  *kz = (int)(i % h);
+  const long long r = i / h;
+  *fy = sfreq((int)(r % n), n);
+  *fx = sfreq((int)(r / n), n);
+}
+
+// kinetic and prior energies on mom_k, delta_k
+__global__ void __launch_bounds__(kThreads) k_energy_k(const ChainDev* __restrict__ ch, int nch,
+                                                        int total) {
+  __shared__ double red[4];
+  for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
+    const ChainDev& d = ch[find_chain(ch, nch, tile, kTileK)];
+    const int lt = tile - d.tb[kTileK];
+    double ak = 0.0, ap = 0.0;
+    for (int j = threadIdx.x; j < kElemPerTile; j += kThreads) {
+      const long long i = (long long)lt * kElemPerTile + j;
+      if (i >= d.nh) break;
+      int fx, fy, kz;
+      kindex(i, d.n, &fx, &fy, &kz);
+      const int m = shell_of(fx, fy, kz, d.n, d.nb);
+      if (m < 0) continue;
+      const double w = (kz == 0 || kz == d.n / 2) ? 1.0 : 2.0;
+      const float2 p = d.pk[i], x = d.dk[i];
+      ak += w * ((double)p.x * p.x + (double)p.y * p.y) * d.td[kDInvMass + m];
+      ap += w * ((double)x.x * x.x + (double)x.y * x.y) * d.td[kDInvLam + m];
+    }
+    const double sk = block_sum(0.5 * ak, red);
+    const double sp = block_sum(0.5 * ap, red);
+    if (threadIdx.x == 0) {
+      d.part[kPartKin * d.maxtiles + lt] = sk;
+      d.part[kPartPri * d.maxtiles + lt] = sp;
+    }
+    __syncthreads();
+  }
+}
+
+// shell sums sigma_m and mode counts n_m (full-grid weights) per tile
+__global__ void __launch_bounds__(kThreads) k_shell_power(const ChainDev* __restrict__ ch,
+                                                           int nch, int total) {
+  __shared__ double bins[4 * kMaxBins];
+  __shared__ double cnt[4 * kMaxBins];
+  for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
+    const ChainDev& d = ch[find_chain(ch, nch, tile, kTileK)];
+    const int lt = tile - d.tb[kTileK];
+    for (int i = threadIdx.x; i < 4 * kMaxBins; i += kThreads) {
+      bins[i] = 0.0;
+      cnt[i] = 0.0;
+    }
+    __syncthreads();
+    const int wv = (threadIdx.x >> 6) * kMaxBins;
+    for (int j = threadIdx.x; j < kElemPerTile; j += kThreads) {
+      const long long i = (long long)lt * kElemPerTile + j;
+      if (i >= d.nh) break;
+      int fx, fy, kz;
+      kindex(i, d.n, &fx, &fy, &kz);
+      const int m = shell_of(fx, fy, kz, d.n, d.nb);
+      if (m < 0) continue;
+      const double w = (kz == 0 || kz == d.n / 2) ? 1.0 : 2.0;
+      const float2 x = d.dk[i];
+      atomicAdd(&bins[wv + m], w * ((double)x.x * x.x + (double)x.y * x.y));
+      atomicAdd(&cnt[wv + m], w);
+    }
+    __syncthreads();
+    for (int m = threadIdx.x; m < d.nb; m += kThreads) {
+      d.shpart[(size_t)lt * d.nb + m] =
+          ((bins[m] + bins[kMaxBins + m]) + bins[2 * kMaxBins + m]) + bins[3 * kMaxBins + m];
+      d.mpart[(size_t)lt * d.nb + m] =
+          ((cnt[m] + cnt[kMaxBins + m]) + cnt[2 * kMaxBins + m]) + cnt[3 * kMaxBins + m];
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(kThreads) k_shell_index(const ChainDev* __restrict__ ch,
+                                                           int total, int16_t* out) {
+  const ChainDev& d = ch[0];
+  for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < d.nh;
+       i += (long long)gridDim.x * kThreads) {
+    int fx, fy, kz;
+    kindex(i, d.n, &fx, &fy, &kz);
+    out[i] = (int16_t)shell_of(fx, fy, kz, d.n, d.nb);
+  }
+}
+
+// Accept/reject bookkeeping on the device: after a density trajectory,
+// rejected chains restore delta_hat and g_hat from the backups, accepted chains
+// take the proposal's real field.  After a joint move, accepted chains rescale
+// delta_hat per shell and take the move's g_hat and real field.
+__global__ void __launch_bounds__(kThreads) k_commit_k(const ChainDev* __restrict__ ch, int nch,
+                                                        int total, int what) {
+  for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
+    const ChainDev& d = ch[find_chain(ch, nch, tile, kTileK)];
+    const int lt = tile - d.tb[kTileK];
+    const bool acc = what == C_HMC ? d.P[kAcc] != 0.0 : d.P[kRjAcc] != 0.0;
+    if (what == C_HMC && acc) continue;
+    if (what == C_RJ && !acc) continue;
+    for (int j = threadIdx.x; j < kElemPerTile; j += kThreads) {
+      const long long i = (long long)lt * kElemPerTile + j;
+      if (i >= d.nh) break;
+      if (what == C_HMC) {
+        d.dk[i] = d.bdk[i];
+        d.gk[i] = d.bgk[i];
+      } else {
+        int fx, fy, kz;
+        kindex(i, d.n, &fx, &fy, &kz);
+        const int m = shell_of(fx, fy, kz, d.n, d.nb);
+        const float s = m >= 0 ? d.tf[kTScale + m] : 0.f;
+        d.dk[i] = cscale(d.dk[i], s);
+        d.gk[i] = d.bgk[i];
+      }
+    }
+  }
+}
+__global__ void __launch_bounds__(kThreads) k_commit_r(const ChainDev* __restrict__ ch, int nch,
+                                                        int total, int what) {
+  for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
+    const ChainDev& d = ch[find_chain(ch, nch, tile, kTileR)];
+    const int lt = tile - d.tb[kTileR];
+    const bool acc = what == C_HMC ? d.P[kAcc] != 0.0 : d.P[kRjAcc] != 0.0;
+    if (!acc) continue;
+    for (int j = threadIdx.x; j < kElemPerTile; j += kThreads) {
+      const long long i = (long long)lt * kElemPerTile + j;
+      if (i >= d.nv) break;
+      d.dr[i] = d.drn[i];
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kThreads) k_copy_real(const ChainDev* __restrict__ ch,
+                                                         int total, const float* src, float* dst) {
+  const ChainDev& d = ch[0];
+  for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < d.nv;
+       i += (long long)gridDim.x * kThreads)
+    dst[i] = src[i];
+}
+
+// ------------------------------------------------------------------ per-chain scalar kernels
+__device__ double tile_sum(const double* p, int n, double* red) {
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += kThreads) acc += p[i];
+  return block_sum(acc, red);
+}
+
+__global__ void __launch_bounds__(kThreads) k_reduce_slot(const ChainDev* __restrict__ ch,
+                                                           int slot, int dst, int cls, int mean) {
+  __shared__ double red[4];
+  const ChainDev& d = ch[blockIdx.x];
+  const double s = tile_sum(d.part + (size_t)slot * d.maxtiles, d.nt[cls], red);
+  if (threadIdx.x == 0) d.P[dst] = mean ? s / (double)d.nv : s;
+}
+
+// Column sums of a per-tile partial matrix [tiles][width], one block per
+// (column, chain), fixed order (strided per thread, then the block tree).
+// mode 0: P[dst + q] = sum (per-shell tables, width nb)
+// mode 1: P[dst + (q % 3) * kMaxSub + q / 3] = sum (moments, width 3 nsub)
+// mode 2: P[dst + q] = sum / 2 + (alpha_prior - 1) (joint-move dU, width nb)
+__global__ void __launch_bounds__(kThreads) k_colsum(const ChainDev* __restrict__ ch, int src,
+                                                      int cls, int dst, int mode) {
+  __shared__ double red[4];
+  const ChainDev& d = ch[blockIdx.y];
+  const int q = blockIdx.x;
+  const int width = mode == 1 ? 3 * d.nsub : d.nb;
+  if (q >= width) return;
+  const double* p = src == 0 ? d.shpart : d.mpart;
+  double acc = 0.0;
+  for (int t = threadIdx.x; t < d.nt[cls]; t += kThreads) acc += p[(size_t)t * width + q];
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) {
+    if (mode == 0) d.P[dst + q] = s;
+    else if (mode == 1) d.P[dst + (q % 3) * kMaxSub + q / 3] = s;
+    else d.P[dst + q] = 0.5 * s + (d.alpha_prior - 1.0);
+  }
+}
+
+// shell tables from lambda and mean(alpha): 1/lambda, 1/m, sqrt(m), m = 1/lambda + abar
+__global__ void k_tables(const ChainDev* __restrict__ ch) {
+  const ChainDev& d = ch[blockIdx.x];
+  const double abar = d.P[kAbar];
+  for (int m = threadIdx.x; m < d.nb; m += blockDim.x) {
+    const double il = 1.0 / d.P[kLam + m];
+    const double ms = il + abar;
+    d.td[kDInvLam + m] = il;
+    d.td[kDInvMass + m] = 1.0 / ms;
+    d.tf[kTInvLam + m] = (float)il;
+    d.tf[kTInvMass + m] = (float)(1.0 / ms);
+    d.tf[kTSqrtMass + m] = (float)sqrt(ms);
+    d.tf[kTScale + m] = 1.f;
+  }
+}
+
+// Metropolis test of eq. acceptance_rule: accept iff ln u < -dH (u: Philox stream 4)
+__global__ void k_accept(const ChainDev* __restrict__ ch, uint32_t traj) {
+  const ChainDev& d = ch[blockIdx.x];
+  if (threadIdx.x != 0) return;
+  const double H0 = d.P[kK0] + d.P[kPi0] + d.P[kDcur];
+  const double H1 = d.P[kK1] + d.P[kPi1] + d.P[kD1];
+  const double dH = H1 - H0;
+  const hmcrng::U4 w = hmcrng::block(d.seed, d.chain, hmcrng::kAccept, traj, 0, 0);
+  const double lu = log(hmcrng::uniform(w.w[0]));
+  const bool finite = isfinite(dH);
+  const bool acc = finite && lu < -dH;
+  d.P[kDH] = dH;
+  d.P[kLogU] = lu;
+  d.P[kAcc] = acc ? 1.0 : 0.0;
+  d.P[kStatus] = finite ? 0.0 : 1.0;
+  if (acc) d.P[kDcur] = d.P[kD1];
+}
+
+// P_m | delta: lambda_m = sigma_m / x_m, x_m ~ chi^2(n_m + 2 alpha - 2) = 2 Gamma(.)
+__global__ void k_draw_power(const ChainDev* __restrict__ ch, uint32_t sweep) {
+  const ChainDev& d = ch[blockIdx.x];
+  for (int m = threadIdx.x; m < d.nb; m += blockDim.x) {
+    const double nm = d.P[kNmodes + m];
+    if (nm <= 0.0) continue;
+    const double beta = nm + 2.0 * d.alpha_prior - 2.0;
+    const double g = hmcsamp::gamma_mt(0.5 * beta, d.seed, d.chain, sweep, (uint32_t)m);
+    if (g > 0.0)
+      d.P[kLam + m] = d.P[kSigma + m] / (2.0 * g);
+    else
+      d.P[kStatus] = 2.0;
+  }
+}
+
+// Nbar^l ~ GIG(1 - N_obs/2, A, B), then b^l ~ N(D/C, 1/C) with the new Nbar^l
+__global__ void k_draw_nbar_bias(const ChainDev* __restrict__ ch, uint32_t sweep) {
+  const ChainDev& d = ch[blockIdx.x];
+  for (int l = threadIdx.x; l < d.nsub; l += blockDim.x) {
+    const double b = d.P[kBias + l];
+    const double S0 = d.P[kS0 + l], Bs = d.P[kBsum + l], nobs = d.P[kNobs + l];
+    const double S1 = d.P[kS1 + l], S2 = d.P[kS2 + l], Ts = d.P[kTsum + l];
+    const double A = S0 + 2.0 * b * S1 + b * b * S2;
+    const double nb = hmcsamp::gig(1.0 - 0.5 * nobs, A, Bs, d.seed, d.chain, sweep, (uint32_t)l);
+    if (nb > 0.0)
+      d.P[kNbar + l] = nb;
+    else
+      d.P[kStatus] = 3.0;
+    if (!((d.fixed_mask >> l) & 1u)) {
+      const double nbl = d.P[kNbar + l];
+      const double C = nbl * S2, D = Ts - nbl * S1;
+      const hmcrng::U4 w = hmcrng::block(d.seed, d.chain, hmcrng::kBias, sweep, (uint32_t)l, 0);
+      double z, unused;
+      hmcrng::box_muller(w.w[0], w.w[1], &z, &unused);
+      d.P[kBias + l] = D / C + z / sqrt(C);
+    }
+  }
+}
+
+// Joint (P, delta) move: HMC in theta_m = ln lambda_m at fixed whitened field.
+// BEGIN: theta0, mass, momenta (stream 8), H0, first half kick and drift.
+// STEP:  kick with dU at the current theta, drift.
+// END:   last half kick, H1, Metropolis test (stream 9), lambda update.
+// dU_m = 1/2 sum_{k in m} w Re(conj(delta_hat) g_hat) + (alpha - 1) from the tile partials.
+__device__ void rj_reflect(double* th, double* rho, double lo, double hi) {
+  for (int it = 0; it < 64; ++it) {
+    if (*th > hi) {
+      *th = 2.0 * hi - *th;
+      *rho = -*rho;
+    } else if (*th < lo) {
+      *th = 2.0 * lo - *th;
+      *rho = -*rho;
+    } else {
+      break;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kThreads) k_rj(const ChainDev* __restrict__ ch, int phase,
+                                                  uint32_t sweep) {
+  __shared__ double red[4];
+  const ChainDev& d = ch[blockIdx.x];
+  const double am1 = d.alpha_prior - 1.0;
+  const int m = threadIdx.x;
+  const bool on = m < d.nb;
+  const double dU = on ? d.P[kDU + m] : 0.0;
+  const double eps = d.eps;
+  if (phase == RJ_BEGIN) {
+    double th = 0.0, rho = 0.0, ms = 1.0;
+    if (on) {
+      th = log(d.P[kLam + m]);
+      ms = fmax(1.0, 0.25 * d.P[kNmodes + m] * d.P[kLam + m] * d.P[kAbar]);
+      const hmcrng::U4 w = hmcrng::block(d.seed, d.chain, hmcrng::kRjMomenta, sweep, 0,
+                                         (uint32_t)(m >> 2));
+      double z0, z1;
+      if ((m & 2) == 0)
+        hmcrng::box_muller(w.w[0], w.w[1], &z0, &z1);
+      else
+        hmcrng::box_muller(w.w[2], w.w[3], &z0, &z1);
+      rho = sqrt(ms) * ((m & 1) ? z1 : z0);
+      d.P[kTheta0 + m] = th;
+      d.P[kMth + m] = ms;
+    }
+    const double k0 = block_sum(on ? 0.5 * rho * rho / ms : 0.0, red);
+    const double st = block_sum(on ? th : 0.0, red);
+    if (m == 0) {
+      d.P[kRjK0] = k0;
+      d.P[kRjU0] = d.P[kDcur] + am1 * st;
+    }
+    if (on) {
+      rho -= 0.5 * eps * dU;
+      th += eps * rho / ms;
+      rj_reflect(&th, &rho, d.P[kLo + m], d.P[kHi + m]);
+      d.P[kTheta + m] = th;
+      d.P[kRho + m] = rho;
+      d.tf[kTScale + m] = (float)exp(0.5 * (th - d.P[kTheta0 + m]));
+    }
+  } else if (phase == RJ_STEP) {
+    if (on) {
+      double th = d.P[kTheta + m], rho = d.P[kRho + m];
+      const double ms = d.P[kMth + m];
+      rho -= eps * dU;
+      th += eps * rho / ms;
+      rj_reflect(&th, &rho, d.P[kLo + m], d.P[kHi + m]);
+      d.P[kTheta + m] = th;
+      d.P[kRho + m] = rho;
+      d.tf[kTScale + m] = (float)exp(0.5 * (th - d.P[kTheta0 + m]));
+    }
+  } else {
+    double th = 0.0, rho = 0.0, ms = 1.0;
+    if (on) {
+      th = d.P[kTheta + m];
+      ms = d.P[kMth + m];
+      rho = d.P[kRho + m] - 0.5 * eps * dU;
+    }
+    const double k1 = block_sum(on ? 0.5 * rho * rho / ms : 0.0, red);
+    const double st = block_sum(on ? th : 0.0, red);
+    __shared__ int acc_s;
+    if (m == 0) {
+      const double H0 = d.P[kRjK0] + d.P[kRjU0];
+      const double H1 = k1 + d.P[kD1] + am1 * st;
+      const double dH = H1 - H0;
+      const hmcrng::U4 w = hmcrng::block(d.seed, d.chain, hmcrng::kRjAccept, sweep, 0, 0);
+      const double lu = log(hmcrng::uniform(w.w[0]));
+      const bool acc = isfinite(dH) && lu < -dH;
+      d.P[kRjDH] = dH;
+      d.P[kRjAcc] = acc ? 1.0 : 0.0;
+      if (acc) d.P[kDcur] = d.P[kD1];
+      acc_s = acc;
+    }
+    __syncthreads();
+    if (on && acc_s) d.P[kLam + m] = exp(th);
+  }
+}
+
+// ------------------------------------------------------------------ launch wrappers
+static inline int eg(int total) { return total < 4096 ? total : 4096; }
+
+void launch_coeff(const ChainDev* ch, int nch, int total, hipStream_t s) {
+  hipLaunchKernelGGL(k_coeff, dim3(eg(total)), dim3(kThreads), 0, s, ch, nch, total);
+}
+void launch_alpha_sum(const ChainDev* ch, int nch, int total, hipStream_t s) {
+  hipLaunchKernelGGL(k_alpha_sum, dim3(eg(total)), dim3(kThreads), 0, s, ch, nch, total);
+}
+void launch_static_moments(const ChainDev* ch, int nch, int total, hipStream_t s) {
+  hipLaunchKernelGGL(k_static_moments, dim3(eg(total)), dim3(kThreads), 0, s, ch, nch, total);
+}
+void launch_moments(const ChainDev* ch, int nch, int total, hipStream_t s) {
+  hipLaunchKernelGGL(k_moments, dim3(eg(total)), dim3(kThreads), 0, s, ch, nch, total);
+}
+void launch_energy_k(const ChainDev* ch, int nch, int total, hipStream_t s) {
+  hipLaunchKernelGGL(k_energy_k, dim3(eg(total)), dim3(kThreads), 0, s, ch, nch, total);
+}
+void launch_energy_r(const ChainDev* ch, int nch, int total, hipStream_t s) {
+  hipLaunchKernelGGL(k_energy_r, dim3(eg(total)), dim3(kThreads), 0, s, ch, nch, total);
+}
+void launch_shell_power(const ChainDev* ch, int nch, int total, hipStream_t s) {
+  hipLaunchKernelGGL(k_shell_power, dim3(eg(total)), dim3(kThreads), 0, s, ch, nch, total);
+}
+void launch_shell_index(const ChainDev* ch, int total, int16_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_shell_index, dim3(eg(total)), dim3(kThreads), 0, s, ch, total, out);
+}
+void launch_commit(int what, const ChainDev* ch, int nch, int total_k, int total_r,
+                   hipStream_t s) {
+  hipLaunchKernelGGL(k_commit_k, dim3(eg(total_k)), dim3(kThreads), 0, s, ch, nch, total_k,
+                     what);
+  hipLaunchKernelGGL(k_commit_r, dim3(eg(total_r)), dim3(kThreads), 0, s, ch, nch, total_r,
+                     what);
+}
+void launch_copy_real(const ChainDev* ch, int total_r, const float* src, float* dst,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_real, dim3(eg(total_r)), dim3(kThreads), 0, s, ch, total_r, src,
+                     dst);
+}
+void launch_reduce_slot(const ChainDev* ch, int nch, int slot, int dst, int cls, hipStream_t s,
+                        bool mean) {
+  hipLaunchKernelGGL(k_reduce_slot, dim3(nch), dim3(kThreads), 0, s, ch, slot, dst, cls,
+                     mean ? 1 : 0);
+}
+void launch_colsum(const ChainDev* ch, int nch, int width, int src, int cls, int dst, int mode,
+                   hipStream_t s) {
+  hipLaunchKernelGGL(k_colsum, dim3(width, nch), dim3(kThreads), 0, s, ch, src, cls, dst, mode);
+}
+void launch_tables(const ChainDev* ch, int nch, hipStream_t s) {
+  hipLaunchKernelGGL(k_tables, dim3(nch), dim3(kMaxBins), 0, s, ch);
+}
+void launch_accept(const ChainDev* ch, int nch, uint32_t traj, hipStream_t s) {
+  hipLaunchKernelGGL(k_accept, dim3(nch), dim3(64), 0, s, ch, traj);
+}
+void launch_draw_power(const ChainDev* ch, int nch, uint32_t sweep, hipStream_t s) {
+  hipLaunchKernelGGL(k_draw_power, dim3(nch), dim3(kMaxBins), 0, s, ch, sweep);
+}
+void launch_draw_nbar_bias(const ChainDev* ch, int nch, uint32_t sweep, hipStream_t s) {
+  hipLaunchKernelGGL(k_draw_nbar_bias, dim3(nch), dim3(64), 0, s, ch, sweep);
+}
+void launch_rj(int phase, const ChainDev* ch, int nch, int nb_max, uint32_t sweep,
+               hipStream_t s) {
+  launch_colsum(ch, nch, nb_max, 0, kTileXY, kDU, 2, s);  // dU from the last x pass
+  hipLaunchKernelGGL(k_rj, dim3(nch), dim3(kThreads), 0, s, ch, phase, sweep);
+}
+
+}  // namespace hmc

@@ -1,0 +1,158 @@
+"""GPU parity: libhmc kernels (through the C-ABI) against the FP64 oracle."""
+import numpy as np
+import pytest
+
+from gpu_common import (chain_spec, coefficients32, mock, oracle_posterior, plain_mock, rel_l2,
+                        start_state)
+from oracle import grid, hmc, model
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1306_1821_amd.binding import Sampler  # noqa: E402
+
+SIZES = [(8, 500.0, 4), (16, 500.0, 8), (32, 500.0, 16), (64, 500.0, 20), (128, 1000.0, 40),
+         (192, 1500.0, 60), (256, 1500.0, 60)]
+
+
+def sampler_for(mk, **kw):
+    return Sampler([chain_spec(mk, **kw)])
+
+
+@pytest.mark.parametrize("n,box,nb", SIZES)
+def test_shell_index_and_counts_bit_exact(n, box, nb):
+    mk = plain_mock(n, box, nb)
+    s = sampler_for(mk)
+    assert np.array_equal(s.shell_index(0).astype(np.int64), grid.half_shells(n, nb))
+    _, nm = s.shell_power(0)
+    assert np.array_equal(nm, grid.mode_counts(n, nb))
+    s.close()
+
+
+@pytest.mark.parametrize("n,box,nb", SIZES)
+def test_shell_power_on_uploaded_state(n, box, nb):
+    mk = plain_mock(n, box, nb)
+    s = sampler_for(mk)
+    rng = np.random.default_rng(n)
+    dk = (rng.standard_normal((n, n, n // 2 + 1)) + 1j * rng.standard_normal((n, n, n // 2 + 1)))
+    dk = dk.astype(np.complex64)
+    s.tensors(0)["delta_k"].copy_(torch.as_tensor(dk))
+    sig, _ = s.shell_power(0)
+    ref = grid.shell_sums(dk.astype(np.complex128), nb)
+    np.testing.assert_allclose(sig, ref, rtol=1e-12)
+    s.close()
+
+
+@pytest.mark.parametrize("n,box,nb", SIZES)
+def test_gradient_and_transforms(n, box, nb):
+    """set_state: delta_hat = F delta, delta_r = F^-1 delta_hat, grad = F(alpha delta - beta)."""
+    mk = plain_mock(n, box, nb, nsub=2)
+    a32, b32 = coefficients32(mk)
+    s = sampler_for(mk)
+    s.set_coefficients(0, a32, b32)
+    d32, dk = start_state(mk)
+    s.set_state(0, d32)
+    st = s.state(0)
+    post = oracle_posterior(mk, a32, b32)
+    f, gk, delta = model.force_k(dk, post.lam_k, post.alpha, post.beta)
+    assert rel_l2(st["delta_k"], dk) < 2e-6
+    assert rel_l2(st["delta_r"], delta) < 2e-6
+    gk_ref = gk.copy()
+    gk_ref[0, 0, 0] = 0.0
+    err = rel_l2(st["grad_k"], gk_ref)
+    print(f"N={n}: gradient rel-L2 {err:.2e}")
+    assert err < 1e-5
+    s.close()
+
+
+@pytest.mark.parametrize("n,box,nb", SIZES)
+def test_hamiltonian_on_identical_arrays(n, box, nb):
+    mk = plain_mock(n, box, nb, nsub=2)
+    a32, b32 = coefficients32(mk)
+    s = sampler_for(mk)
+    s.set_coefficients(0, a32, b32)
+    rng = np.random.default_rng(7 + n)
+    h = n // 2 + 1
+    dk = (0.3 * (rng.standard_normal((n, n, h)) + 1j * rng.standard_normal((n, n, h)))).astype(np.complex64)
+    pk = (rng.standard_normal((n, n, h)) + 1j * rng.standard_normal((n, n, h))).astype(np.complex64)
+    dr = (0.5 * rng.standard_normal((n, n, n))).astype(np.float32)
+    t = s.tensors(0)
+    t["delta_k"].copy_(torch.as_tensor(dk))
+    t["mom_k"].copy_(torch.as_tensor(pk))
+    t["delta_r"].copy_(torch.as_tensor(dr))
+    got = s.hamiltonian(0)
+    post = oracle_posterior(mk, a32, b32)
+    ref = hmc.energies(dk.astype(np.complex128), pk.astype(np.complex128), dr.astype(np.float64), post)
+    print(f"N={n}: energies {got} vs {ref}")
+    for g, r in zip(got, ref):
+        assert abs(g - r) < max(1e-6, 1e-13 * abs(r))
+    s.close()
+
+
+TRAJ_CASES = [("tiny8x2", 0.1, 10), ("small16", 0.1, 10), ("cfg1", 0.05, 20), (64, 0.05, 10),
+              (128, 0.04, 8)]
+
+
+def traj_mock(case):
+    if isinstance(case, str):
+        return mock(case)
+    return plain_mock(case, 500.0 if case == 64 else 1000.0, 20 if case == 64 else 40, nsub=2)
+
+
+@pytest.mark.parametrize("case,eps,nsteps", TRAJ_CASES)
+def test_trajectory_matches_oracle(case, eps, nsteps):
+    mk = traj_mock(case)
+    n = mk["cfg"].n
+    a32, b32 = coefficients32(mk)
+    s = sampler_for(mk, eps=eps, nsteps=nsteps, seed=17)
+    s.set_coefficients(0, a32, b32)
+    d32, dk = start_state(mk)
+    s.set_state(0, d32)
+    post = oracle_posterior(mk, a32, b32, workers=4)
+    for traj in range(2):
+        before = s.state(0)
+        dH, acc = s.trajectory(traj)
+        st = s.state(0)
+        ref = hmc.trajectory(before["delta_k"].astype(np.complex128), post, eps, nsteps, 17, 0, traj)
+        e_p = rel_l2(st["mom_k"], ref["p1"])
+        margin = abs(ref["log_u"] + ref["dH"])
+        print(f"N={n} traj {traj}: dH gpu {dH[0]:.6e} oracle {ref['dH']:.6e} "
+              f"|diff| {abs(dH[0] - ref['dH']):.2e}; p rel-L2 {e_p:.2e}; acc {acc[0]} {ref['accepted']}")
+        assert e_p < 1e-4
+        if n == 8:
+            assert abs(dH[0] - ref["dH"]) < 1e-5
+        if margin > 1e-2:
+            assert bool(acc[0]) == ref["accepted"]
+        if acc[0] and ref["accepted"]:
+            assert rel_l2(st["delta_k"], ref["proposal"]) < 1e-4
+            assert rel_l2(st["grad_k"], np.where(post.shells >= 0, ref["grad1"], 0)) < 1e-4
+        if not acc[0]:
+            assert np.array_equal(st["delta_k"], before["delta_k"])
+            assert np.array_equal(st["delta_r"], before["delta_r"])
+    s.close()
+
+
+def test_batched_mixed_sizes_match_oracle():
+    """Chains of 8^3, 16^3 and 32^3 advance in the same launches; each matches the oracle."""
+    names = ["tiny8x2", "small16", "cfg1"]
+    mks = [mock(x) for x in names]
+    specs = [chain_spec(m, eps=0.05, nsteps=10, seed=5, chain_id=i) for i, m in enumerate(mks)]
+    s = Sampler(specs)
+    posts = []
+    for i, m in enumerate(mks):
+        a32, b32 = coefficients32(m)
+        s.set_coefficients(i, a32, b32)
+        d32, _ = start_state(m)
+        s.set_state(i, d32)
+        posts.append(oracle_posterior(m, a32, b32))
+    befores = [s.state(i)["delta_k"] for i in range(3)]
+    dH, acc = s.trajectory(3)
+    for i in range(3):
+        ref = hmc.trajectory(befores[i].astype(np.complex128), posts[i], 0.05, 10, 5, i, 3)
+        st = s.state(i)
+        assert rel_l2(st["mom_k"], ref["p1"]) < 1e-4, i
+        assert abs(dH[i] - ref["dH"]) < 1e-3 * max(1.0, abs(ref["dH"])), i
+    s.close()
