@@ -56,6 +56,9 @@ def lib(path=LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise FileNotFoundError(f"{path} is missing: build it with python -m paper_1306_1821_amd.build")
+    # PyTorch bundles its own HIP runtime; load it first so that libhmc binds to
+    # the same runtime (one HIP runtime per process).
+    import torch  # noqa: F401
     L = ctypes.CDLL(path)
     P, D, I32, U64 = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int32, ctypes.c_uint64
     L.hmc_workspace_bytes.argtypes = [ctypes.POINTER(HmcConfig)]

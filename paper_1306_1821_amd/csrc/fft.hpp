@@ -19,6 +19,10 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#ifndef HMC_TW_POW2
+#define HMC_TW_POW2 1
+#endif
+
 namespace hmcfft {
 
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
@@ -190,12 +194,36 @@ __device__ __forceinline__ void stage(float2* v, float2* lds, int es, int t, boo
     for (int r = 0; r < R; ++r) a[r] = v[q + r * Q];
     if constexpr (NS > 1) {
       constexpr int step = N / (NS * R);
+#if HMC_TW_POW2
+    if constexpr (N >= 128) {
+      // large N: twiddles W^(r k) for every r from the table entries at powers of
+      // two of r (at most three complex products each, fewer live registers)
+      float2 wp[5];
+#pragma unroll
+      for (int b = 0; (1 << b) < R; ++b) wp[b] = tw[(1 << b) * k * step];
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        float2 w = make_float2(1.f, 0.f);
+        bool first = true;
+#pragma unroll
+        for (int b = 0; (1 << b) < R; ++b)
+          if (r & (1 << b)) {
+            w = first ? wp[b] : cmul(w, wp[b]);
+            first = false;
+          }
+        if (DIR < 0) w.y = -w.y;
+        a[r] = cmul(a[r], w);
+      }
+    } else
+#endif
+    {
 #pragma unroll
       for (int r = 1; r < R; ++r) {
         float2 w = tw[r * k * step];
         if (DIR < 0) w.y = -w.y;
         a[r] = cmul(a[r], w);
       }
+    }
     }
     DFT<R, DIR>::run(a);
     if constexpr (LAST) {

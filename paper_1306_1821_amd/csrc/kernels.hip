@@ -18,8 +18,44 @@
 #include "rng.hpp"
 #include "samplers.hpp"
 
+#ifndef HMC_NT
+#define HMC_NT 1
+#endif
+#ifndef HMC_PREFETCH
+#define HMC_PREFETCH 0
+#endif
+#ifndef HMC_CFG256
+#define HMC_CFG256 1
+#endif
+#ifndef HMC_XCD
+#define HMC_XCD 1
+#endif
+
 namespace hmc {
 using namespace hmcfft;
+
+// Loads/stores of the streamed state (delta_hat, p_hat, alpha, beta): with
+// HMC_NT they carry the non-temporal hint so that they do not displace the
+// intermediate grid from the caches.
+typedef float f2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float2 ld_s(const float2* p) {
+#if HMC_NT
+  const f2v v = __builtin_nontemporal_load(reinterpret_cast<const f2v*>(p));
+  return make_float2(v.x, v.y);
+#else
+  return *p;
+#endif
+}
+__device__ __forceinline__ void st_s(float2* p, float2 v) {
+#if HMC_NT
+  f2v w;
+  w.x = v.x;
+  w.y = v.y;
+  __builtin_nontemporal_store(w, reinterpret_cast<f2v*>(p));
+#else
+  *p = v;
+#endif
+}
 
 // ------------------------------------------------------------------ configs
 // strided C2C passes (x and y): T threads per pencil, B pencils per block
@@ -30,7 +66,11 @@ template <> struct XC<32>  { static constexpr int T = 4,  B = 64;  using RL = Ra
 template <> struct XC<64>  { static constexpr int T = 8,  B = 32;  using RL = Radices<8, 8>; };
 template <> struct XC<128> { static constexpr int T = 8,  B = 32;  using RL = Radices<16, 8>; };
 template <> struct XC<192> { static constexpr int T = 16, B = 16;  using RL = Radices<4, 4, 12>; };
+#if HMC_CFG256 == 1
+template <> struct XC<256> { static constexpr int T = 32, B = 8;   using RL = Radices<8, 8, 4>; };
+#else
 template <> struct XC<256> { static constexpr int T = 16, B = 16;  using RL = Radices<16, 16>; };
+#endif
 // z pass: half-length complex transform of M = N/2 points per row
 template <int N> struct ZC;
 template <> struct ZC<8>   { static constexpr int T = 1, B = 256; using RL = Radices<4>; };
@@ -39,7 +79,11 @@ template <> struct ZC<32>  { static constexpr int T = 4, B = 64;  using RL = Rad
 template <> struct ZC<64>  { static constexpr int T = 4, B = 64;  using RL = Radices<8, 4>; };
 template <> struct ZC<128> { static constexpr int T = 8, B = 32;  using RL = Radices<8, 8>; };
 template <> struct ZC<192> { static constexpr int T = 8, B = 32;  using RL = Radices<4, 4, 6>; };
+#if HMC_CFG256 == 1
+template <> struct ZC<256> { static constexpr int T = 16, B = 16; using RL = Radices<8, 4, 4>; };
+#else
 template <> struct ZC<256> { static constexpr int T = 8, B = 32;  using RL = Radices<16, 8>; };
+#endif
 
 template <int N> constexpr int xlds() { return N * (XC<N>::B + 1) * 8; }
 template <int N> constexpr int zlds() { return ZC<N>::B * (N / 2 + 2) * 8; }
@@ -82,6 +126,20 @@ __device__ __forceinline__ int find_chain(const ChainDev* ch, int nch, int tile,
 }
 
 __device__ __forceinline__ int sfreq(int k, int n) { return k <= n / 2 ? k : k - n; }
+
+// Tile handled by block b of a grid of g blocks.  Workgroups are dealt to the
+// 8 XCDs round-robin; with HMC_XCD, XCD x takes a contiguous run of tiles so
+// that neighbouring tiles (which share cache lines at their edges) hit the
+// same L2.
+__device__ __forceinline__ int tile_of(int b, int g) {
+#if HMC_XCD
+  const int q = g >> 3, r = g & 7, x = b & 7, i = b >> 3;
+  return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+#else
+  (void)g;
+  return b;
+#endif
+}
 
 // Shell of a mode with signed integer frequencies: the m with
 // m^2 q_max < nb^2 q <= (m+1)^2 q_max, q_max = 3 (n/2)^2; -1 for q = 0.
@@ -147,6 +205,16 @@ __device__ __forceinline__ void xpass(const ChainDev& d, int lt, const XArgs a, 
   const bool dot = (MODE == X_FWD) && (a.flags & XF_DOT);
   if (dot) bins_zero(bins);
 
+  constexpr bool pre = HMC_PREFETCH && MODE == X_STEP;
+  float2 pdk[pre ? E : 1], ppk[pre ? E : 1];
+  if constexpr (pre) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const size_t idx = (size_t)(t + T * e) * stride + col;
+      pdk[e] = active ? ld_s(d.dk + idx) : make_float2(0.f, 0.f);
+      ppk[e] = active ? ld_s(d.pk + idx) : make_float2(0.f, 0.f);
+    }
+  }
   if constexpr (MODE != X_INV) {
 #pragma unroll
     for (int e = 0; e < E; ++e)
@@ -180,7 +248,12 @@ __device__ __forceinline__ void xpass(const ChainDev& d, int lt, const XArgs a, 
     } else {
       // X_START, X_STEP, X_END: kick (and drift)
       float2 dk = make_float2(0.f, 0.f), pk = make_float2(0.f, 0.f), g;
-      if (active) dk = d.dk[idx];
+      if constexpr (pre) {
+        dk = pdk[e];
+        pk = ppk[e];
+      } else if (active) {
+        dk = ld_s(d.dk + idx);
+      }
       if constexpr (MODE == X_START) {
         // fresh momentum p_hat = sqrt(m_k) F w; gradient of the current state from memory
         const float sq = m >= 0 ? d.tf[kTSqrtMass + m] : 0.f;
@@ -196,7 +269,7 @@ __device__ __forceinline__ void xpass(const ChainDev& d, int lt, const XArgs a, 
         }
       } else {
         g = cscale(v[e], norm);
-        if (active) pk = d.pk[idx];
+        if (!pre && active) pk = ld_s(d.pk + idx);
       }
       if (m >= 0) {
         const float il = d.tf[kTInvLam + m];
@@ -222,8 +295,8 @@ __device__ __forceinline__ void xpass(const ChainDev& d, int lt, const XArgs a, 
         }
       } else {
         if (active) {
-          d.dk[idx] = dk;
-          d.pk[idx] = pk;
+          st_s(d.dk + idx, dk);
+          st_s(d.pk + idx, pk);
         }
         v[e] = cscale(dk, norm);
       }
@@ -277,7 +350,8 @@ __global__ void __launch_bounds__(kThreads) k_xpass_n(const ChainDev* __restrict
   extern __shared__ float2 lds[];
   __shared__ double red[4];
   __shared__ double bins[4 * kMaxBins];
-  for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
+  for (int b = blockIdx.x; b < total; b += gridDim.x) {
+    const int tile = gridDim.x == total ? tile_of(b, total) : b;
     const int c = find_chain(ch, nch, tile, kTileXY);
     const ChainDev& d = ch[c];
     xpass<N, MODE>(d, tile - d.tb[kTileXY], a, tw, lds, red, bins);
@@ -326,7 +400,8 @@ template <int N, int DIR>
 __global__ void __launch_bounds__(kThreads) k_ypass_n(const ChainDev* __restrict__ ch, int nch,
                                                        int total, const float2* __restrict__ tw) {
   extern __shared__ float2 lds[];
-  for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
+  for (int b = blockIdx.x; b < total; b += gridDim.x) {
+    const int tile = gridDim.x == total ? tile_of(b, total) : b;
     const int c = find_chain(ch, nch, tile, kTileXY);
     const ChainDev& d = ch[c];
     ypass<N, DIR>(d, tile - d.tb[kTileXY], tw, lds);
@@ -397,9 +472,9 @@ __device__ __forceinline__ void zpass(const ChainDev& d, int lt, const ZArgs a, 
       const float2 x = v[e];
       if (active && drout) reinterpret_cast<float2*>(drout + rbase)[n] = x;
       if (MODE == Z_GRAD || (a.flags & ZF_DATA)) {
-        const float2 al = active ? reinterpret_cast<const float2*>(d.alpha + rbase)[n]
+        const float2 al = active ? ld_s(reinterpret_cast<const float2*>(d.alpha + rbase) + n)
                                  : make_float2(0.f, 0.f);
-        const float2 be = active ? reinterpret_cast<const float2*>(d.beta + rbase)[n]
+        const float2 be = active ? ld_s(reinterpret_cast<const float2*>(d.beta + rbase) + n)
                                  : make_float2(0.f, 0.f);
         if (active && (a.flags & ZF_DATA))
           dat += (0.5 * al.x * x.x - be.x) * (double)x.x + (0.5 * al.y * x.y - be.y) * (double)x.y;
@@ -462,7 +537,8 @@ __global__ void __launch_bounds__(kThreads) k_zpass_n(const ChainDev* __restrict
                                                        const float2* __restrict__ tw) {
   extern __shared__ float2 lds[];
   __shared__ double red[4];
-  for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
+  for (int b = blockIdx.x; b < total; b += gridDim.x) {
+    const int tile = gridDim.x == total ? tile_of(b, total) : b;
     const int c = find_chain(ch, nch, tile, kTileZ);
     const ChainDev& d = ch[c];
     zpass<N, MODE>(d, tile - d.tb[kTileZ], a, tw, lds, red);

@@ -309,8 +309,9 @@ hmc_status hmc_init_batch(const hmc_config* cfg, const hmc_buffers* buf, int32_t
         const double a = -2.0 * M_PI * (double)i / (double)L;
         tw[tw_offset(L) + i] = make_float2((float)std::cos(a), (float)std::sin(a));
       }
-    if (hipMalloc(&c->tw, kTwTotal * sizeof(float2)) != hipSuccess) {
-      c->err = "hipMalloc twiddles";
+    const hipError_t e = hipMalloc(&c->tw, kTwTotal * sizeof(float2));
+    if (e != hipSuccess) {
+      c->err = std::string("hipMalloc twiddles: ") + hipGetErrorString(e);
       return bail(HMC_EDEVICE);
     }
     if (hipMemcpy(c->tw, tw.data(), kTwTotal * sizeof(float2), hipMemcpyHostToDevice) !=

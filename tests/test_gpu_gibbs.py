@@ -1,0 +1,101 @@
+"""GPU parity of whole block sweeps (density HMC, P, joint move, Nbar, b) with the oracle."""
+import numpy as np
+import pytest
+
+from gpu_common import chain_spec, mock, plain_mock, start_state
+from oracle import gibbs, model
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1306_1821_amd.binding import Sampler  # noqa: E402
+
+
+def oracle_cfg(mk, spec):
+    cfg = mk["cfg"]
+    lam = model.lambdas(mk["pk_init"], cfg.n, cfg.box)
+    return dict(n=cfg.n, box=cfg.box, nb=cfg.nb, eps=spec["eps"], nsteps=spec["nsteps"],
+                alpha_prior=1.0, seed=spec["seed"], chain=spec.get("chain_id", 0),
+                fixed_mask=spec["fixed_mask"], rj=spec["rj"], lam_lo=lam * np.exp(-10.0),
+                lam_hi=lam * np.exp(10.0), workers=4)
+
+
+CASES = [("tiny8x2", False, 0.1, 8), ("small16", False, 0.08, 10), ("small16", True, 0.08, 10),
+         ("cfg1", False, 0.05, 20), ("cfg1", True, 0.05, 20), (64, True, 0.04, 10)]
+
+
+def case_mock(name):
+    return mock(name) if isinstance(name, str) else plain_mock(name, 500.0, 20, nsub=3)
+
+
+@pytest.mark.parametrize("name,rj,eps,nsteps", CASES)
+def test_sweeps_match_oracle(name, rj, eps, nsteps):
+    mk = case_mock(name)
+    spec = chain_spec(mk, eps=eps, nsteps=nsteps, seed=23, rj=rj, fixed_mask=1)
+    s = Sampler([spec])
+    d32, dk = start_state(mk)
+    s.set_state(0, d32)
+    ocfg = oracle_cfg(mk, spec)
+    data = dict(R=mk["R"].astype(np.float64), counts=mk["counts"].astype(np.float64))
+    state = dict(dk=dk, pk=mk["pk_init"].copy(), bias=mk["bias"].copy(), nbar=mk["nbar"].copy())
+    for sw in range(3):
+        g = s.sweep(sw)[0]
+        o = gibbs.sweep(state, data, ocfg, sw)
+        print(f"{name} rj={rj} sweep {sw}: dH {g['dH']:.5e}/{o['dH']:.5e} acc {g['accepted']}/"
+              f"{o['accepted']} rj_dH {g['rj_dH']:.4e}/{o.get('rj_dH', 0):.4e} "
+              f"P rel {np.max(np.abs(g['pk'] / o['pk'] - 1)):.2e} "
+              f"Nbar rel {np.max(np.abs(g['nbar'] / o['nbar'] - 1)):.2e} "
+              f"b rel {np.max(np.abs(g['bias'] / o['bias'] - 1)):.2e}")
+        assert g["accepted"] == o["accepted"]
+        assert abs(g["dH"] - o["dH"]) < 1e-3 * max(1.0, abs(o["dH"]))
+        if rj:
+            assert g["rj_accepted"] == o["rj_accepted"]
+            assert abs(g["rj_dH"] - o["rj_dH"]) < 1e-3 * max(1.0, abs(o["rj_dH"]))
+        np.testing.assert_allclose(g["pk"], o["pk"], rtol=1e-4)
+        np.testing.assert_allclose(g["nbar"], o["nbar"], rtol=1e-5)
+        np.testing.assert_allclose(g["bias"], o["bias"], rtol=1e-4)
+        state = dict(dk=o["dk"], pk=o["pk"], bias=o["bias"], nbar=o["nbar"])
+    s.close()
+
+
+def test_sweeps_are_bit_reproducible():
+    """Same inputs, seed and sweep indices give bit-identical chains (no reduction races)."""
+    mk = mock("small16")
+    outs = []
+    for _ in range(2):
+        s = Sampler([chain_spec(mk, eps=0.08, nsteps=10, seed=29, rj=True)])
+        d32, _ = start_state(mk)
+        s.set_state(0, d32)
+        trace = [s.sweep(i)[0] for i in range(4)]
+        outs.append((trace, s.state(0)["delta_k"]))
+        s.close()
+    for a, b in zip(outs[0][0], outs[1][0]):
+        assert a["dH"] == b["dH"] and np.array_equal(a["pk"], b["pk"])
+        assert np.array_equal(a["nbar"], b["nbar"]) and np.array_equal(a["bias"], b["bias"])
+    assert np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_batched_sweeps_match_single_chains():
+    """A mixed-size batch advances each chain exactly as its own context does."""
+    mks = [mock("tiny8x2"), mock("small16"), mock("cfg1")]
+    specs = [chain_spec(m, eps=0.05, nsteps=8, seed=31, chain_id=i, rj=True)
+             for i, m in enumerate(mks)]
+    b = Sampler(specs)
+    singles = [Sampler([sp]) for sp in specs]
+    for i, m in enumerate(mks):
+        d32, _ = start_state(m)
+        b.set_state(i, d32)
+        singles[i].set_state(0, d32)
+    for sw in range(2):
+        gb = b.sweep(sw)
+        for i in range(3):
+            gs = singles[i].sweep(sw)[0]
+            assert gb[i]["accepted"] == gs["accepted"]
+            np.testing.assert_allclose(gb[i]["pk"], gs["pk"], rtol=1e-6)
+            np.testing.assert_allclose(gb[i]["nbar"], gs["nbar"], rtol=1e-6)
+    b.close()
+    for s in singles:
+        s.close()
