@@ -8,7 +8,8 @@
   units lambda of ``model`` (P_phys = lambda V / N_vox); a chi^2_beta variate is
   drawn as 2 Gamma(beta/2) by Marsaglia & Tsang (2000) rather than as a sum of
   beta squared normals (same law, O(1) random numbers per shell); shells with
-  n_m = 0 keep their value.
+  n_m = 0 or sigma_m = 0 (an all-zero field, where the conditional is
+  improper) keep their value.
 * Nbar^l | delta, b (Sec. "The Nbar posterior distribution", Appendix A): GIG
   with p = 1 - N_obs/2, A = sum R (1 + b delta)^2, B = sum N^2 / R (eq. GIG_post).
   Readings: N_obs counts voxels with R^l > 0 (the main-text form; the appendix
@@ -20,7 +21,8 @@
   normal with variance 1/C, mean D/C.  Completing the square of eq.
   galaxybias_post gives C = sum Nbar R delta^2 and D = sum (N - Nbar R) delta;
   the printed forms (sum Nbar R delta in the main-text variance, (N - Nbar) in
-  D) are read as typos.  A mask holds chosen biases fixed: b, delta and P are
+  D) are read as typos.  For delta = 0 on every observed voxel (C = 0) the
+  conditional is improper and b is kept.  A mask holds chosen biases fixed: b, delta and P are
   degenerate under (k b, delta / k, P / k^2), and the paper's own test fixes
   one reference bias.
 * Block order (eq. multiblock and the flowchart disagree): density HMC, P,
@@ -66,7 +68,7 @@ def draw_power(sigma, n_modes, lam_old, alpha_prior, seed, chain, sweep):
     """New lambda_m = sigma_m / x_m, x_m ~ chi^2(n_m + 2 alpha - 2); sub = m."""
     lam = np.array(lam_old, dtype=np.float64)
     for m in range(len(sigma)):
-        if n_modes[m] == 0:
+        if n_modes[m] == 0 or not sigma[m] > 0:   # improper conditional: keep P_m
             continue
         beta = n_modes[m] + 2.0 * alpha_prior - 2.0
         x = 2.0 * gamma_mt(0.5 * beta, seed, chain, sweep, m)
@@ -168,7 +170,7 @@ def draw_bias(mom, nbar, bias_old, fixed_mask, seed, chain, sweep):
     """New b^l ~ N(D/C, 1/C) for subsamples not held fixed (sub = l)."""
     out = np.array(bias_old, dtype=np.float64)
     for l, (S1, S2, T) in enumerate(mom):
-        if (fixed_mask >> l) & 1:
+        if (fixed_mask >> l) & 1 or not S2 > 0:  # S2 = 0 (delta = 0): improper, keep b
             continue
         C = nbar[l] * S2
         D = T - nbar[l] * S1

@@ -119,3 +119,12 @@ def test_nbar_conditional_matches_likelihood_profile():
                        for x in xs])
     gig = (1 - 0.5 * nobs - 1) * np.log(xs) - 0.5 * (A * xs + B / xs)
     assert np.ptp(direct - gig) < 1e-8 * np.max(np.abs(direct))
+
+
+def test_degenerate_field_keeps_power_and_bias():
+    """delta = 0 gives sigma_m = 0 and C = 0: both conditionals are improper, values kept."""
+    lam = gibbs.draw_power(np.zeros(2), np.array([26, 152]), [3.0, 4.0], 1.0, 4, 0, 0)
+    assert np.array_equal(lam, [3.0, 4.0])
+    mom = [(0.0, 0.0, 0.0), (0.0, 0.0, 0.0)]
+    b = gibbs.draw_bias(mom, np.array([5.0, 1.0]), np.array([1.0, 1.4]), 0, 8, 0, 0)
+    assert np.array_equal(b, [1.0, 1.4])
