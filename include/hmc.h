@@ -183,6 +183,14 @@ hmc_status hmc_shell_index(hmc_ctx* ctx, int32_t chain, int16_t* out_dev);
  * paper's Fourier-diagonal mass. */
 hmc_status hmc_set_mass(hmc_ctx* ctx, int32_t chain, const float* logvar_dev);
 
+/* Graph replay: with enable = 1, leapfrog_trajectory and gibbs_sweep record
+ * their device work once into a HIP graph on a library-owned stream (default
+ * priority, ordered after and before the caller's stream by events) and replay
+ * it on later calls; the trajectory or sweep index is passed through device
+ * memory, so one graph serves every index.  enable = 0 returns to direct
+ * launches.  Pass timing (hmc_timing) does not see graph replays. */
+hmc_status hmc_use_graph(hmc_ctx* ctx, int32_t enable);
+
 /* Device timing of the leapfrog passes (tracing).  enable = 1 starts
  * recording HIP events on the context's stream around every launch of the
  * step passes and clears the totals; enable = 0 stops recording; enable = -1

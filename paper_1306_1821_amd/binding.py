@@ -44,7 +44,7 @@ class HmcSweepStats(ctypes.Structure):
 EXPORTS = ["hmc_workspace_bytes", "hmc_init", "hmc_init_batch", "leapfrog_trajectory",
            "hamiltonian", "shell_power", "gibbs_sweep", "hmc_set_state", "hmc_set_params",
            "hmc_set_coefficients", "hmc_get_params", "hmc_shell_index", "hmc_set_mass",
-           "hmc_timing", "hmc_last_error", "hmc_destroy"]
+           "hmc_timing", "hmc_use_graph", "hmc_last_error", "hmc_destroy"]
 
 _lib = None
 
@@ -78,6 +78,7 @@ def lib(path=LIB_PATH):
     L.hmc_shell_index.argtypes = [P, I32, P]
     L.hmc_set_mass.argtypes = [P, I32, P]
     L.hmc_timing.argtypes = [P, I32, D, ctypes.POINTER(ctypes.c_int64)]
+    L.hmc_use_graph.argtypes = [P, I32]
     L.hmc_last_error.argtypes = [P]
     L.hmc_last_error.restype = ctypes.c_char_p
     L.hmc_destroy.argtypes = [P]
@@ -247,6 +248,10 @@ class Sampler:
         out = self.torch.empty((n, n, n // 2 + 1), dtype=self.torch.int16, device=self.device)
         self._check(self.L.hmc_shell_index(self.ctx, chain, ctypes.c_void_p(out.data_ptr())))
         return out.cpu().numpy()
+
+    def use_graph(self, enable=True):
+        """Replay trajectories / sweeps from captured HIP graphs."""
+        self._check(self.L.hmc_use_graph(self.ctx, int(bool(enable))))
 
     def timing(self, enable=-1):
         """Summed device milliseconds and launch counts of the step passes

@@ -93,6 +93,7 @@ struct ChainDev {
   float* tf;       // float shell tables (kTSize)
   double* td;      // float64 shell tables (kDSize)
   const float* lmass;  // learned real-space mass factor sqrt(D_i), or null
+  const uint32_t* draw;  // device counter: Philox draw index of the current trajectory/sweep
 };
 
 // Twiddle tables W_L^i = exp(-2 pi i i / L), float2, for every supported

@@ -453,7 +453,7 @@ __device__ __forceinline__ void zpass(const ChainDev& d, int lt, const ZArgs a, 
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const uint64_t vox = rbase + 2 * (uint64_t)(t + T * e);
-      const hmcrng::U4 w = hmcrng::block(d.seed, d.chain, hmcrng::kMomenta, a.draw, 0,
+      const hmcrng::U4 w = hmcrng::block(d.seed, d.chain, hmcrng::kMomenta, *d.draw, 0,
                                          (uint32_t)(vox >> 2));
       double z0, z1;
       if (((vox >> 1) & 1) == 0)
@@ -959,9 +959,10 @@ __global__ void k_tables(const ChainDev* __restrict__ ch) {
 }
 
 // Metropolis test of eq. acceptance_rule: accept iff ln u < -dH (u: Philox stream 4)
-__global__ void k_accept(const ChainDev* __restrict__ ch, uint32_t traj) {
+__global__ void k_accept(const ChainDev* __restrict__ ch) {
   const ChainDev& d = ch[blockIdx.x];
   if (threadIdx.x != 0) return;
+  const uint32_t traj = *d.draw;
   const double H0 = d.P[kK0] + d.P[kPi0] + d.P[kDcur];
   const double H1 = d.P[kK1] + d.P[kPi1] + d.P[kD1];
   const double dH = H1 - H0;
@@ -977,11 +978,13 @@ __global__ void k_accept(const ChainDev* __restrict__ ch, uint32_t traj) {
 }
 
 // P_m | delta: lambda_m = sigma_m / x_m, x_m ~ chi^2(n_m + 2 alpha - 2) = 2 Gamma(.)
-__global__ void k_draw_power(const ChainDev* __restrict__ ch, uint32_t sweep) {
+__global__ void k_draw_power(const ChainDev* __restrict__ ch) {
   const ChainDev& d = ch[blockIdx.x];
+  const uint32_t sweep = *d.draw;
   for (int m = threadIdx.x; m < d.nb; m += blockDim.x) {
     const double nm = d.P[kNmodes + m];
-    if (nm <= 0.0) continue;
+    // an empty shell or a field with no power in it leaves P_m unchanged
+    if (nm <= 0.0 || !(d.P[kSigma + m] > 0.0)) continue;
     const double beta = nm + 2.0 * d.alpha_prior - 2.0;
     const double g = hmcsamp::gamma_mt(0.5 * beta, d.seed, d.chain, sweep, (uint32_t)m);
     if (g > 0.0)
@@ -992,8 +995,9 @@ __global__ void k_draw_power(const ChainDev* __restrict__ ch, uint32_t sweep) {
 }
 
 // Nbar^l ~ GIG(1 - N_obs/2, A, B), then b^l ~ N(D/C, 1/C) with the new Nbar^l
-__global__ void k_draw_nbar_bias(const ChainDev* __restrict__ ch, uint32_t sweep) {
+__global__ void k_draw_nbar_bias(const ChainDev* __restrict__ ch) {
   const ChainDev& d = ch[blockIdx.x];
+  const uint32_t sweep = *d.draw;
   for (int l = threadIdx.x; l < d.nsub; l += blockDim.x) {
     const double b = d.P[kBias + l];
     const double S0 = d.P[kS0 + l], Bs = d.P[kBsum + l], nobs = d.P[kNobs + l];
@@ -1004,7 +1008,7 @@ __global__ void k_draw_nbar_bias(const ChainDev* __restrict__ ch, uint32_t sweep
       d.P[kNbar + l] = nb;
     else
       d.P[kStatus] = 3.0;
-    if (!((d.fixed_mask >> l) & 1u)) {
+    if (!((d.fixed_mask >> l) & 1u) && S2 > 0.0) {  // S2 = 0: degenerate, b kept
       const double nbl = d.P[kNbar + l];
       const double C = nbl * S2, D = Ts - nbl * S1;
       const hmcrng::U4 w = hmcrng::block(d.seed, d.chain, hmcrng::kBias, sweep, (uint32_t)l, 0);
@@ -1034,10 +1038,10 @@ __device__ void rj_reflect(double* th, double* rho, double lo, double hi) {
   }
 }
 
-__global__ void __launch_bounds__(kThreads) k_rj(const ChainDev* __restrict__ ch, int phase,
-                                                  uint32_t sweep) {
+__global__ void __launch_bounds__(kThreads) k_rj(const ChainDev* __restrict__ ch, int phase) {
   __shared__ double red[4];
   const ChainDev& d = ch[blockIdx.x];
+  const uint32_t sweep = *d.draw;
   const double am1 = d.alpha_prior - 1.0;
   const int m = threadIdx.x;
   const bool on = m < d.nb;
@@ -1162,19 +1166,24 @@ void launch_colsum(const ChainDev* ch, int nch, int width, int src, int cls, int
 void launch_tables(const ChainDev* ch, int nch, hipStream_t s) {
   hipLaunchKernelGGL(k_tables, dim3(nch), dim3(kMaxBins), 0, s, ch);
 }
-void launch_accept(const ChainDev* ch, int nch, uint32_t traj, hipStream_t s) {
-  hipLaunchKernelGGL(k_accept, dim3(nch), dim3(64), 0, s, ch, traj);
+__global__ void k_set_draw(uint32_t* p, uint32_t v) {
+  if (threadIdx.x == 0) *p = v;
 }
-void launch_draw_power(const ChainDev* ch, int nch, uint32_t sweep, hipStream_t s) {
-  hipLaunchKernelGGL(k_draw_power, dim3(nch), dim3(kMaxBins), 0, s, ch, sweep);
+void launch_set_draw(uint32_t* p, uint32_t v, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_draw, dim3(1), dim3(64), 0, s, p, v);
 }
-void launch_draw_nbar_bias(const ChainDev* ch, int nch, uint32_t sweep, hipStream_t s) {
-  hipLaunchKernelGGL(k_draw_nbar_bias, dim3(nch), dim3(64), 0, s, ch, sweep);
+void launch_accept(const ChainDev* ch, int nch, hipStream_t s) {
+  hipLaunchKernelGGL(k_accept, dim3(nch), dim3(64), 0, s, ch);
 }
-void launch_rj(int phase, const ChainDev* ch, int nch, int nb_max, uint32_t sweep,
-               hipStream_t s) {
+void launch_draw_power(const ChainDev* ch, int nch, hipStream_t s) {
+  hipLaunchKernelGGL(k_draw_power, dim3(nch), dim3(kMaxBins), 0, s, ch);
+}
+void launch_draw_nbar_bias(const ChainDev* ch, int nch, hipStream_t s) {
+  hipLaunchKernelGGL(k_draw_nbar_bias, dim3(nch), dim3(64), 0, s, ch);
+}
+void launch_rj(int phase, const ChainDev* ch, int nch, int nb_max, hipStream_t s) {
   launch_colsum(ch, nch, nb_max, 0, kTileXY, kDU, 2, s);  // dU from the last x pass
-  hipLaunchKernelGGL(k_rj, dim3(nch), dim3(kThreads), 0, s, ch, phase, sweep);
+  hipLaunchKernelGGL(k_rj, dim3(nch), dim3(kThreads), 0, s, ch, phase);
 }
 
 }  // namespace hmc

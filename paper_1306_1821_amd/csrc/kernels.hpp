@@ -29,7 +29,7 @@ struct XArgs {
 };
 struct ZArgs {
   int flags;
-  uint32_t draw;
+  uint32_t unused;
   const float* src;  // Z_R2C input (single-chain launches)
 };
 
@@ -70,10 +70,13 @@ void launch_reduce_slot(const ChainDev* ch, int nch, int slot, int dst, int cls,
 void launch_colsum(const ChainDev* ch, int nch, int width, int src, int cls, int dst, int mode,
                    hipStream_t s);
 void launch_tables(const ChainDev* ch, int nch, hipStream_t s);
-void launch_accept(const ChainDev* ch, int nch, uint32_t traj, hipStream_t s);
-void launch_draw_power(const ChainDev* ch, int nch, uint32_t sweep, hipStream_t s);
-void launch_draw_nbar_bias(const ChainDev* ch, int nch, uint32_t sweep, hipStream_t s);
-void launch_rj(int phase, const ChainDev* ch, int nch, int nb_max, uint32_t sweep, hipStream_t s);
+// the Philox draw index (trajectory or sweep) lives in device memory so that a
+// captured graph can be replayed for any index
+void launch_set_draw(uint32_t* p, uint32_t v, hipStream_t s);
+void launch_accept(const ChainDev* ch, int nch, hipStream_t s);
+void launch_draw_power(const ChainDev* ch, int nch, hipStream_t s);
+void launch_draw_nbar_bias(const ChainDev* ch, int nch, hipStream_t s);
+void launch_rj(int phase, const ChainDev* ch, int nch, int nb_max, hipStream_t s);
 
 enum Commit : int { C_HMC = 0, C_RJ = 1 };
 enum RjPhase : int { RJ_BEGIN = 0, RJ_STEP = 1, RJ_END = 2 };

@@ -100,6 +100,12 @@ struct hmc_ctx {
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_used;
   double t_ms[4] = {0, 0, 0, 0};
   long long t_n[4] = {0, 0, 0, 0};
+  // Philox draw index in device memory; graph replay of trajectories / sweeps
+  uint32_t* d_draw = nullptr;
+  bool use_graph = false;
+  hipStream_t gstream = nullptr;
+  hipEvent_t gev_a = nullptr, gev_b = nullptr;
+  hipGraphExec_t g_traj = nullptr, g_sweep = nullptr;
   std::string err;
   std::vector<double> stat_pk, stat_bias, stat_nbar;
 };
@@ -175,9 +181,9 @@ struct Seq {
     launch_ypass(dir, d, nch, tot[kTileXY], c->lds_x, c->tw, c->grid_cap, s, un);
     tm.done(s);
   }
-  void z(int mode, int flags, uint32_t draw = 0, const float* src = nullptr) {
+  void z(int mode, int flags, const float* src = nullptr) {
     Timed tm(c, mode == Z_GRAD ? 2 : 3, s);
-    launch_zpass(mode, d, nch, tot[kTileZ], c->lds_z, ZArgs{flags, draw, src}, c->tw,
+    launch_zpass(mode, d, nch, tot[kTileZ], c->lds_z, ZArgs{flags, 0, src}, c->tw,
                  c->grid_cap, s, un);
     tm.done(s);
   }
@@ -240,6 +246,48 @@ static hmc_status refresh_coefficients(hmc_ctx* c) {
   return check_launch(c);
 }
 
+static hmc_status run_trajectory(hmc_ctx* c);
+static hmc_status run_sweep(hmc_ctx* c);
+
+// Capture `body` once on the library's side stream and replay the graph; the
+// side stream is ordered after and before the caller's stream with events.
+static hmc_status run_graph(hmc_ctx* c, hipGraphExec_t* exec, hmc_status (*body)(hmc_ctx*)) {
+  if (!c->gstream) {
+    HIPCHK(c, hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking));
+    HIPCHK(c, hipEventCreateWithFlags(&c->gev_a, hipEventDisableTiming));
+    HIPCHK(c, hipEventCreateWithFlags(&c->gev_b, hipEventDisableTiming));
+  }
+  if (!*exec) {
+    hipStream_t saved = c->stream;
+    const bool timing = c->timing;
+    c->stream = c->gstream;
+    c->timing = false;
+    hipError_t e = hipStreamBeginCapture(c->gstream, hipStreamCaptureModeThreadLocal);
+    hmc_status st = e == hipSuccess ? body(c) : HMC_EDEVICE;
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(c->gstream, &g);
+    c->stream = saved;
+    c->timing = timing;
+    if (e != hipSuccess || e2 != hipSuccess || st != HMC_OK || !g) {
+      if (g) (void)hipGraphDestroy(g);
+      return fail(c, HMC_EDEVICE, std::string("graph capture failed: ") +
+                                      hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    e = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      *exec = nullptr;
+      return fail(c, HMC_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+    }
+  }
+  HIPCHK(c, hipEventRecord(c->gev_a, c->stream));
+  HIPCHK(c, hipStreamWaitEvent(c->gstream, c->gev_a, 0));
+  HIPCHK(c, hipGraphLaunch(*exec, c->gstream));
+  HIPCHK(c, hipEventRecord(c->gev_b, c->gstream));
+  HIPCHK(c, hipStreamWaitEvent(c->stream, c->gev_b, 0));
+  return HMC_OK;
+}
+
 extern "C" {
 
 size_t hmc_workspace_bytes(const hmc_config* cfg) {
@@ -260,6 +308,12 @@ void hmc_destroy(hmc_ctx* ctx) {
     (void)hipEventDestroy(u.second.second);
   }
   for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
+  if (ctx->g_traj) (void)hipGraphExecDestroy(ctx->g_traj);
+  if (ctx->g_sweep) (void)hipGraphExecDestroy(ctx->g_sweep);
+  if (ctx->gev_a) (void)hipEventDestroy(ctx->gev_a);
+  if (ctx->gev_b) (void)hipEventDestroy(ctx->gev_b);
+  if (ctx->gstream) (void)hipStreamDestroy(ctx->gstream);
+  if (ctx->d_draw) (void)hipFree(ctx->d_draw);
   for (auto& k : ctx->ch) {
     (void)hipFree(k.dev.P);
     (void)hipFree(k.dev.tf);
@@ -320,6 +374,10 @@ hmc_status hmc_init_batch(const hmc_config* cfg, const hmc_buffers* buf, int32_t
       return bail(HMC_EDEVICE);
     }
   }
+  if (hipMalloc(&c->d_draw, 64) != hipSuccess) {
+    c->err = "hipMalloc draw counter";
+    return bail(HMC_EDEVICE);
+  }
   if (hipHostMalloc((void**)&c->pinned, 64 * sizeof(double), 0) != hipSuccess) {
     c->err = "hipHostMalloc";
     return bail(HMC_EDEVICE);
@@ -353,6 +411,7 @@ hmc_status hmc_init_batch(const hmc_config* cfg, const hmc_buffers* buf, int32_t
       base[j] += d.nt[j];
     }
     d.maxtiles = L.maxtiles;
+    d.draw = c->d_draw;
     d.R = k.buf.R;
     d.counts = k.buf.counts;
     d.dk = (float2*)k.buf.delta_k;
@@ -438,10 +497,12 @@ hmc_status hmc_init(const hmc_config* cfg, const hmc_buffers* buf, const double*
 }
 
 // one density trajectory for every chain; results stay on the device
-static hmc_status run_trajectory(hmc_ctx* c, uint32_t traj) {
+// one density trajectory for every chain (draw index from the device counter);
+// no host synchronisation, so it can be captured in a graph
+static hmc_status run_trajectory(hmc_ctx* c) {
   Seq q = seq_all(c);
   const int nch = (int)c->ch.size();
-  q.z(Z_NOISE, 0, traj);
+  q.z(Z_NOISE, 0);
   q.y(+1);
   q.x(X_START, 0.5f, 1.f, 0);
   launch_reduce_slot(c->d_all, nch, kPartKin, kK0, kTileXY, c->stream);
@@ -459,14 +520,15 @@ static hmc_status run_trajectory(hmc_ctx* c, uint32_t traj) {
   launch_reduce_slot(c->d_all, nch, kPartKin, kK1, kTileXY, c->stream);
   launch_reduce_slot(c->d_all, nch, kPartPri, kPi1, kTileXY, c->stream);
   launch_reduce_slot(c->d_all, nch, kPartDat, kD1, kTileZ, c->stream);
-  launch_accept(c->d_all, nch, traj, c->stream);
+  launch_accept(c->d_all, nch, c->stream);
   launch_commit(C_HMC, c->d_all, nch, c->total[kTileK], c->total[kTileR], c->stream);
   return check_launch(c);
 }
 
 hmc_status leapfrog_trajectory(hmc_ctx* c, uint64_t traj_index, double* dH, int32_t* accepted) {
   if (!c) return fail(nullptr, HMC_EINVAL, "null context");
-  hmc_status st = run_trajectory(c, (uint32_t)traj_index);
+  launch_set_draw(c->d_draw, (uint32_t)traj_index, c->stream);
+  hmc_status st = c->use_graph ? run_graph(c, &c->g_traj, run_trajectory) : run_trajectory(c);
   if (st != HMC_OK) return st;
   if ((st = pull_params(c)) != HMC_OK) return st;
   bool numeric = false;
@@ -512,38 +574,37 @@ hmc_status shell_power(hmc_ctx* c, int32_t chain, double* sigma, int64_t* n_mode
   return HMC_OK;
 }
 
-hmc_status gibbs_sweep(hmc_ctx* c, uint64_t sweep_index, hmc_sweep_stats* out) {
-  if (!c) return fail(nullptr, HMC_EINVAL, "null context");
-  const uint32_t s = (uint32_t)sweep_index;
+// the device part of one block sweep for every chain (no host synchronisation)
+static hmc_status run_sweep(hmc_ctx* c) {
   const int nch = (int)c->ch.size();
-  hmc_status st = run_trajectory(c, s);
+  hmc_status st = run_trajectory(c);
   if (st != HMC_OK) return st;
   // P | delta
   launch_shell_power(c->d_all, nch, c->total[kTileK], c->stream);
   launch_colsum(c->d_all, nch, c->max_nb, 0, kTileK, kSigma, 0, c->stream);
-  launch_draw_power(c->d_all, nch, s, c->stream);
+  launch_draw_power(c->d_all, nch, c->stream);
   launch_tables(c->d_all, nch, c->stream);
   // joint (P, delta) move for chains that ask for it (all or none in a batch)
   bool any_rj = false;
   for (auto& k : c->ch) any_rj |= k.cfg.rj_move != 0;
   if (any_rj) {
     Seq q = seq_all(c);
-    // dU at the start: per-shell Re(conj(delta_hat) g_hat) from the stored gradient
+    // dU at the start: per-shell Re(conj(delta_hat) g_hat) at the current state
     q.x(X_INV, 0.f, 0.f, 0);
     q.y(-1);
     q.z(Z_GRAD, 0);
     q.y(+1);
     q.x(X_FWD, 0.f, 0.f, XF_DOT | XF_NOSTORE);
-    launch_rj(RJ_BEGIN, c->d_all, nch, c->max_nb, s, c->stream);
+    launch_rj(RJ_BEGIN, c->d_all, nch, c->max_nb, c->stream);
     for (int i = 0; i < c->nsteps; ++i) {
       const bool last = i == c->nsteps - 1;
       q.gradient(last ? (ZF_WRITE_DRN | ZF_DATA) : 0,
                  XF_SCALE | XF_DOT | (last ? XF_OUT_ALT : XF_NOSTORE));
       if (!last) {
-        launch_rj(RJ_STEP, c->d_all, nch, c->max_nb, s, c->stream);
+        launch_rj(RJ_STEP, c->d_all, nch, c->max_nb, c->stream);
       } else {
         launch_reduce_slot(c->d_all, nch, kPartDat, kD1, kTileZ, c->stream);
-        launch_rj(RJ_END, c->d_all, nch, c->max_nb, s, c->stream);
+        launch_rj(RJ_END, c->d_all, nch, c->max_nb, c->stream);
       }
     }
     launch_commit(C_RJ, c->d_all, nch, c->total[kTileK], c->total[kTileR], c->stream);
@@ -552,10 +613,17 @@ hmc_status gibbs_sweep(hmc_ctx* c, uint64_t sweep_index, hmc_sweep_stats* out) {
   // Nbar | delta, b and b | delta, Nbar
   launch_moments(c->d_all, nch, c->total[kTileR], c->stream);
   launch_colsum(c->d_all, nch, 3 * c->max_sub, 1, kTileR, kS1, 1, c->stream);
-  launch_draw_nbar_bias(c->d_all, nch, s, c->stream);
+  launch_draw_nbar_bias(c->d_all, nch, c->stream);
   // alpha, beta, mass and gradient for the new parameters
   if ((st = refresh_coefficients(c)) != HMC_OK) return st;
-  if ((st = refresh_gradient(c, false)) != HMC_OK) return st;
+  return refresh_gradient(c, false);
+}
+
+hmc_status gibbs_sweep(hmc_ctx* c, uint64_t sweep_index, hmc_sweep_stats* out) {
+  if (!c) return fail(nullptr, HMC_EINVAL, "null context");
+  launch_set_draw(c->d_draw, (uint32_t)sweep_index, c->stream);
+  hmc_status st = c->use_graph ? run_graph(c, &c->g_sweep, run_sweep) : run_sweep(c);
+  if (st != HMC_OK) return st;
   if ((st = pull_params(c)) != HMC_OK) return st;
   c->stat_pk.clear();
   c->stat_bias.clear();
@@ -667,6 +735,12 @@ hmc_status hmc_shell_index(hmc_ctx* c, int32_t chain, int16_t* out_dev) {
   hmc_status st = check_launch(c);
   if (st != HMC_OK) return st;
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  return HMC_OK;
+}
+
+hmc_status hmc_use_graph(hmc_ctx* c, int32_t enable) {
+  if (!c) return fail(nullptr, HMC_EINVAL, "null context");
+  c->use_graph = enable != 0;
   return HMC_OK;
 }
 
