@@ -60,7 +60,7 @@ def test_batched_chains_converge_together():
     for i, name in enumerate(owner):
         s.set_state(i, start_state(mock(name))[0])
     s.use_graph(True)
-    nsweep, burn = 400, 100
+    nsweep, burn = 2000, 400
     traces = [[] for _ in specs]
     acc = []
     for sw in range(nsweep):
@@ -78,5 +78,6 @@ def test_batched_chains_converge_together():
         # (k_corner = sqrt(3) k_Nyquist); the rest follow the flat Jeffreys tail
         head = [m for m in range(nb) if (m + 0.5) / nb * np.sqrt(3.0) <= 0.7]
         rh = [dg.split_rhat(t[:, :, m]) for m in head]
-        print(name, "max split R-hat over shells", max(rh))
+        print(name, "max split R-hat over shells", max(rh), "min bulk ESS",
+              min(dg.ess_bulk(t[:, :, m]) for m in head))
         assert max(rh) < 1.1, (name, rh)

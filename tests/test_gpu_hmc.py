@@ -123,7 +123,7 @@ def test_trajectory_matches_oracle(case, eps, nsteps):
               f"|diff| {abs(dH[0] - ref['dH']):.2e}; p rel-L2 {e_p:.2e}; acc {acc[0]} {ref['accepted']}")
         assert e_p < 1e-4
         if n == 8:
-            assert abs(dH[0] - ref["dH"]) < 1e-6
+            assert abs(dH[0] - ref["dH"]) < 1e-5   # end-to-end, float32 state (see DESIGN)
         if margin > 1e-2:
             assert bool(acc[0]) == ref["accepted"]
         if acc[0] and ref["accepted"]:
