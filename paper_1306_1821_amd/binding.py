@@ -44,7 +44,9 @@ class HmcSweepStats(ctypes.Structure):
 EXPORTS = ["hmc_workspace_bytes", "hmc_init", "hmc_init_batch", "leapfrog_trajectory",
            "hamiltonian", "shell_power", "gibbs_sweep", "hmc_set_state", "hmc_set_params",
            "hmc_set_coefficients", "hmc_get_params", "hmc_shell_index", "hmc_set_mass",
-           "hmc_timing", "hmc_use_graph", "hmc_last_error", "hmc_destroy"]
+           "hmc_timing", "hmc_use_graph", "hmc_last_error", "hmc_destroy",
+           "cnn_param_count", "cnn_create", "cnn_get_params", "cnn_forward", "cnn_gradient",
+           "cnn_train_step", "cnn_last_error", "cnn_destroy"]
 
 _lib = None
 
@@ -83,8 +85,21 @@ def lib(path=LIB_PATH):
     L.hmc_last_error.restype = ctypes.c_char_p
     L.hmc_destroy.argtypes = [P]
     L.hmc_destroy.restype = None
+    F = ctypes.POINTER(ctypes.c_float)
+    L.cnn_param_count.argtypes = []
+    L.cnn_param_count.restype = ctypes.c_size_t
+    L.cnn_create.argtypes = [F, P, ctypes.POINTER(P)]
+    L.cnn_get_params.argtypes = [P, F]
+    L.cnn_forward.argtypes = [P, I32, P, P, P]
+    L.cnn_gradient.argtypes = [P, I32, P, P, F, D]
+    L.cnn_train_step.argtypes = [P, I32, P, P, ctypes.c_float, D]
+    L.cnn_last_error.argtypes = [P]
+    L.cnn_last_error.restype = ctypes.c_char_p
+    L.cnn_destroy.argtypes = [P]
+    L.cnn_destroy.restype = None
     for name in EXPORTS:
-        if name not in ("hmc_workspace_bytes", "hmc_last_error", "hmc_destroy"):
+        if name not in ("hmc_workspace_bytes", "hmc_last_error", "hmc_destroy", "cnn_param_count",
+                        "cnn_last_error", "cnn_destroy"):
             getattr(L, name).restype = ctypes.c_int32
     _lib = L
     return L
@@ -271,3 +286,94 @@ class Sampler:
 def _dptr_out(a):
     assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+CNN_LAYERS = [(3, 16), (16, 16), (16, 16), (16, 2)]
+
+
+def cnn_flatten(params):
+    """[(W [27, ci, co], b [co]), ...] -> flat float32 vector (include/cnn.h layout)."""
+    return np.concatenate([np.concatenate([np.asarray(W, np.float32).ravel(),
+                                           np.asarray(b, np.float32).ravel()]) for W, b in params])
+
+
+def cnn_unflatten(flat):
+    out, o = [], 0
+    for ci, co in CNN_LAYERS:
+        W = flat[o:o + 27 * ci * co].reshape(27, ci, co)
+        o += 27 * ci * co
+        out.append((W, flat[o:o + co]))
+        o += co
+    return out
+
+
+class CNN:
+    """The warm-start / mass network (include/cnn.h) on one GPU."""
+
+    def __init__(self, params, device="cuda:0", stream=None):
+        import torch
+        self.torch = torch
+        self.L = lib()
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        flat = cnn_flatten(params) if isinstance(params, (list, tuple)) else np.asarray(params, np.float32)
+        if flat.size != self.L.cnn_param_count():
+            raise HmcError(-1, "wrong number of CNN parameters")
+        torch.cuda.synchronize(self.device)
+        ctx = ctypes.c_void_p()
+        st = self.L.cnn_create(flat.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                               ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx))
+        if st != HMC_OK:
+            raise HmcError(st, self.L.cnn_last_error(None).decode())
+        self.ctx = ctx
+
+    def _check(self, st):
+        if st != HMC_OK:
+            raise HmcError(st, self.L.cnn_last_error(self.ctx).decode())
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.L.cnn_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _dev(self, a):
+        return self.torch.as_tensor(np.asarray(a, dtype=np.float32)).to(self.device).contiguous() \
+            if not isinstance(a, self.torch.Tensor) else a.contiguous()
+
+    def params(self):
+        out = np.zeros(self.L.cnn_param_count(), dtype=np.float32)
+        self._check(self.L.cnn_get_params(self.ctx, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return out
+
+    def forward(self, inputs):
+        """inputs: [3, N, N, N] -> (mu, logvar) device tensors."""
+        x = self._dev(inputs)
+        n = x.shape[-1]
+        mu = self.torch.empty((n, n, n), dtype=self.torch.float32, device=self.device)
+        lv = self.torch.empty_like(mu)
+        self._check(self.L.cnn_forward(self.ctx, n, ctypes.c_void_p(x.data_ptr()),
+                                       ctypes.c_void_p(mu.data_ptr()), ctypes.c_void_p(lv.data_ptr())))
+        return mu, lv
+
+    def gradient(self, inputs, target):
+        x, t = self._dev(inputs), self._dev(target)
+        g = np.zeros(self.L.cnn_param_count(), dtype=np.float32)
+        loss = ctypes.c_double()
+        self._check(self.L.cnn_gradient(self.ctx, x.shape[-1], ctypes.c_void_p(x.data_ptr()),
+                                        ctypes.c_void_p(t.data_ptr()),
+                                        g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                        ctypes.byref(loss)))
+        return g, loss.value
+
+    def train_step(self, inputs, target, lr):
+        x, t = self._dev(inputs), self._dev(target)
+        loss = ctypes.c_double()
+        self._check(self.L.cnn_train_step(self.ctx, x.shape[-1], ctypes.c_void_p(x.data_ptr()),
+                                          ctypes.c_void_p(t.data_ptr()), float(lr), ctypes.byref(loss)))
+        return loss.value

@@ -13,7 +13,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libhmc.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "runtime.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "runtime.hip", "cnn.hip")]
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
