@@ -177,10 +177,14 @@ hmc_status hmc_get_params(hmc_ctx* ctx, int32_t chain, double* pk, double* bias,
  * int16, -1 for k = 0), as the kernels compute it. */
 hmc_status hmc_shell_index(hmc_ctx* ctx, int32_t chain, int16_t* out_dev);
 
-/* Elementwise diagonal mass in real space (learned mass): with logvar_dev a
- * device [N][N][N] float32 log-variance v, the inverse mass becomes
- * D^(1/2) F^-1 diag(1/m_k) F D^(1/2) with D = v / mean(v).  NULL restores the
- * paper's Fourier-diagonal mass. */
+/* Learned mass (the mass affects only efficiency, text after eq. Mass_matrix):
+ * with logvar_dev a device [N][N][N] float32 log-variance s and
+ * D = exp(s) / mean(exp(s)), the inverse mass on the zero-mean field becomes
+ * T T^T with T = P D^(1/2) F^-1 diag(m_k^-1/2), P the mean projector, i.e.
+ * P D^(1/2) F^-1 diag(1/m_k) F D^(1/2) P; D = 1 is the paper's Fourier-diagonal
+ * mass.  A step then costs two more real transforms.  NULL restores the plain
+ * mass.  Every chain of a context must use the same kind of mass
+ * (HMC_EUNSUPPORTED otherwise; trajectories keep the plain mass). */
 hmc_status hmc_set_mass(hmc_ctx* ctx, int32_t chain, const float* logvar_dev);
 
 /* Graph replay: with enable = 1, leapfrog_trajectory and gibbs_sweep record

@@ -94,3 +94,71 @@ def trajectory(dk, post, eps, nsteps, seed, chain, traj):
     return dict(p0=pk0, e0=e0, e1=e1, dH=dH, accepted=acc, log_u=float(np.log(u)),
                 proposal=dk1, p1=pk1, grad1=gk1, delta1=delta1,
                 state=dk1 if acc else dk)
+
+
+# --------------------------------------------------------------------------- learned mass
+# The mass only affects efficiency (text after eq. Mass_matrix).  The learned
+# variant keeps the Fourier diagonal m_k and adds a real-space diagonal D from
+# the network's variance.  Because the mean mode is frozen, the field is written
+# delta = T z with T = P D^(1/2) F^-1 diag(m_k^-1/2) (P removes the mean) and z
+# moves with unit mass, so the inverse mass on delta is T T^T =
+# P D^(1/2) F^-1 diag(1/m_k) F D^(1/2) P (symmetric on the zero-mean subspace).
+# Carrying the momentum as p_hat = sqrt(m_k) pi_hat (pi conjugate to z):
+#   p ~ N(0, M)  is  p_hat = sqrt(m_k) F w (as for the plain mass),
+#   kinetic      1/2 sum_k |p_hat|^2 / m_k,
+#   kick         p_hat -= eps F(D^(1/2) P grad psi),
+#   drift        delta_hat += eps [F(D^(1/2) F^-1(p_hat / m_k))]_{k != 0},
+# grad psi = F^-1(delta_hat / lambda) + alpha delta - beta.  D = 1 gives the
+# plain leapfrog.
+
+def learned_force(dk, post, sqrtD):
+    """F(D^(1/2) P grad psi) with the k = 0 entry zeroed; also returns delta."""
+    n = post.n
+    sel = post.shells >= 0
+    delta = grid.inv(dk, n, post.workers)
+    prior = grid.inv(np.where(sel, dk / np.where(sel, post.lam_k, 1.0), 0.0), n, post.workers)
+    g = prior + post.alpha * delta - post.beta
+    g = g - g.mean()                                   # P grad psi
+    f = grid.fwd(sqrtD * g, post.workers)
+    f[0, 0, 0] = 0.0
+    return f, delta
+
+
+def learned_velocity(pk, post, sqrtD):
+    """F(D^(1/2) F^-1(p_hat' / m_k)) with the k = 0 entry zeroed."""
+    n = post.n
+    sel = post.shells >= 0
+    q = grid.inv(np.where(sel, pk / np.where(sel, post.mass_k, 1.0), 0.0), n, post.workers)
+    u = grid.fwd(sqrtD * q, post.workers)
+    u[0, 0, 0] = 0.0
+    return u
+
+
+def leapfrog_learned(dk, pk, post, sqrtD, eps, nsteps):
+    """KDK with the learned mass; returns (delta_hat, p_hat', delta) at the end."""
+    f, delta = learned_force(dk, post, sqrtD)
+    pk = pk - 0.5 * eps * f
+    for s in range(nsteps):
+        dk = dk + eps * learned_velocity(pk, post, sqrtD)
+        f, delta = learned_force(dk, post, sqrtD)
+        pk = pk - (eps if s < nsteps - 1 else 0.5 * eps) * f
+    return dk, pk, delta
+
+
+def mass_factor(logvar):
+    """D^(1/2) with D = v / mean(v), v = exp(logvar)."""
+    v = np.exp(np.asarray(logvar, dtype=np.float64))
+    return np.sqrt(v / v.mean())
+
+
+def trajectory_learned(dk, post, sqrtD, eps, nsteps, seed, chain, traj):
+    pk0 = draw_momentum(post, seed, chain, traj)
+    delta0 = grid.inv(dk, post.n, post.workers)
+    e0 = energies(dk, pk0, delta0, post)
+    dk1, pk1, delta1 = leapfrog_learned(dk, pk0, post, sqrtD, eps, nsteps)
+    e1 = energies(dk1, pk1, delta1, post)
+    dH = sum(e1) - sum(e0)
+    u = philox.uniform(seed, chain, philox.STREAM_ACCEPT, traj)
+    acc = bool(np.log(u) < -dH)
+    return dict(p0=pk0, e0=e0, e1=e1, dH=dH, accepted=acc, log_u=float(np.log(u)),
+                proposal=dk1, p1=pk1, delta1=delta1, state=dk1 if acc else dk)

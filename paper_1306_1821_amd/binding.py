@@ -250,6 +250,17 @@ class Sampler:
                                                 ctypes.c_void_p(b.data_ptr())))
         self.torch.cuda.synchronize(self.device)
 
+    def set_mass(self, chain, logvar=None):
+        """Install the learned mass from a log-variance field (None: plain mass)."""
+        if logvar is None:
+            self._check(self.L.hmc_set_mass(self.ctx, chain, None))
+            return
+        x = logvar if isinstance(logvar, self.torch.Tensor) else \
+            self.torch.as_tensor(np.asarray(logvar, dtype=np.float32))
+        x = x.to(self.device, dtype=self.torch.float32).contiguous()
+        self._check(self.L.hmc_set_mass(self.ctx, chain, ctypes.c_void_p(x.data_ptr())))
+        self.torch.cuda.synchronize(self.device)
+
     def get_params(self, chain=0):
         c = self.chains[chain]
         pk = np.zeros(c["nb"])

@@ -27,7 +27,7 @@ enum POff : int {
   kK0 = 1, kPi0 = 2, kK1 = 3, kPi1 = 4, kD1 = 5,
   kDH = 6, kAcc = 7, kAbar = 8, kLogU = 9,
   kRjDH = 10, kRjAcc = 11, kRjU0 = 12, kRjK0 = 13, kStatus = 14, kDnew = 15,
-  kRjStep = 16, kHK = 17, kHP = 18, kHD = 19,
+  kRjStep = 16, kHK = 17, kHP = 18, kHD = 19, kGbar = 20, kLmean = 21,
   // arrays
   kLam = 32,                       // lambda_m (unitary), nb
   kSigma = kLam + kMaxBins,        // sigma_m, nb
@@ -94,6 +94,11 @@ struct ChainDev {
   double* td;      // float64 shell tables (kDSize)
   const float* lmass;  // learned real-space mass factor sqrt(D_i), or null
   const uint32_t* draw;  // device counter: Philox draw index of the current trajectory/sweep
+  // learned mass: two more intermediate grids, F(D^(1/2)) and D^(1/2) per voxel
+  float2* T2;
+  float2* T3;
+  float2* shat;
+  float* smass;
 };
 
 // Twiddle tables W_L^i = exp(-2 pi i i / L), float2, for every supported

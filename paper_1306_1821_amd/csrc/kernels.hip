@@ -236,7 +236,10 @@ __device__ __forceinline__ void xpass(const ChainDev& d, int lt, const XArgs a, 
     } else if constexpr (MODE == X_FWD) {
       float2 g = m < 0 ? make_float2(0.f, 0.f) : cscale(v[e], norm);
       if (active && !(a.flags & XF_NOSTORE)) {
-        float2* out = (a.flags & XF_OUT_DK) ? d.dk : (a.flags & XF_OUT_ALT) ? d.bgk : d.gk;
+        float2* out = (a.flags & XF_OUT_DK)     ? d.dk
+                      : (a.flags & XF_OUT_ALT)  ? d.bgk
+                      : (a.flags & XF_OUT_SHAT) ? d.shat
+                                                : d.gk;
         out[idx] = g;
       }
       if (dot && active && m >= 0) {
@@ -360,7 +363,8 @@ __global__ void __launch_bounds__(kThreads) k_xpass_n(const ChainDev* __restrict
 
 // ------------------------------------------------------------------ y pass
 template <int N, int DIR>
-__device__ __forceinline__ void ypass(const ChainDev& d, int lt, const float2* __restrict__ twall, float2* lds) {
+__device__ __forceinline__ void ypass(const ChainDev& d, int lt, const float2* __restrict__ twall, float2* lds,
+                                      int buf) {
   using C = XC<N>;
   constexpr int T = C::T, B = C::B, E = N / T, H = N / 2 + 1, ES = B + 1;
   const float2* tw = twall + tw_offset(N);
@@ -368,7 +372,7 @@ __device__ __forceinline__ void ypass(const ChainDev& d, int lt, const float2* _
   const int p = lt * B + b;
   const bool active = p < N * H;
   const int x = active ? p / H : 0, kz = active ? p % H : 0;
-  float2* base = d.T + (size_t)x * N * H + kz;
+  float2* base = (buf == 0 ? d.T : buf == 1 ? d.T2 : d.T3) + (size_t)x * N * H + kz;
   float2 v[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) v[e] = active ? base[(size_t)(t + T * e) * H] : make_float2(0.f, 0.f);
@@ -381,14 +385,15 @@ __device__ __forceinline__ void ypass(const ChainDev& d, int lt, const float2* _
 
 template <int DIR>
 __global__ void __launch_bounds__(kThreads) k_ypass(const ChainDev* __restrict__ ch, int nch,
-                                                     int total, const float2* __restrict__ tw) {
+                                                     int total, const float2* __restrict__ tw,
+                                                     int buf) {
   extern __shared__ float2 lds[];
   for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
     const int c = find_chain(ch, nch, tile, kTileXY);
     const ChainDev& d = ch[c];
     const int lt = tile - d.tb[kTileXY];
     switch (d.n) {
-#define C(NN) case NN: ypass<NN, DIR>(d, lt, tw, lds); break;
+#define C(NN) case NN: ypass<NN, DIR>(d, lt, tw, lds, buf); break;
       HMC_FOR_N(C)
 #undef C
       default: break;
@@ -398,13 +403,14 @@ __global__ void __launch_bounds__(kThreads) k_ypass(const ChainDev* __restrict__
 
 template <int N, int DIR>
 __global__ void __launch_bounds__(kThreads) k_ypass_n(const ChainDev* __restrict__ ch, int nch,
-                                                       int total, const float2* __restrict__ tw) {
+                                                       int total, const float2* __restrict__ tw,
+                                                       int buf) {
   extern __shared__ float2 lds[];
   for (int b = blockIdx.x; b < total; b += gridDim.x) {
     const int tile = gridDim.x == total ? tile_of(b, total) : b;
     const int c = find_chain(ch, nch, tile, kTileXY);
     const ChainDev& d = ch[c];
-    ypass<N, DIR>(d, tile - d.tb[kTileXY], tw, lds);
+    ypass<N, DIR>(d, tile - d.tb[kTileXY], tw, lds, buf);
   }
 }
 
@@ -545,6 +551,296 @@ __global__ void __launch_bounds__(kThreads) k_zpass_n(const ChainDev* __restrict
   }
 }
 
+
+// ------------------------------------------------------------------ learned mass
+// Inverse mass T T^T, T = P D^(1/2) F^-1 diag(m_k^-1/2) (P removes the mean):
+//   drift  delta_hat += eps [F(D^(1/2) F^-1(p_hat / m_k))]_{k != 0}
+//   kick   p_hat -= eps F(D^(1/2) P grad psi),
+//          grad psi = F^-1(delta_hat / lambda) + alpha delta - beta;
+// F(D^(1/2) P g) = F(D^(1/2) g) - mean(g) F(D^(1/2)), with mean(g) from the
+// real-space pass partials and F(D^(1/2)) precomputed.  A step is
+//   x L_DRIFT (T2 -> drift -> delta_hat, inverse x of delta_hat -> T and of
+//   delta_hat/lambda -> T3), y-1 T, y-1 T3, z LZ_FORCE (T, T3 -> T), y+1 T,
+//   x L_KICK (T -> kick -> inverse x of p_hat/m -> T2), y-1 T2, z LZ_VEL, y+1 T2.
+
+// C2R of one half-complex row into v (v[e] = (x_2n, x_2n+1), n = t + T e).
+template <int N>
+__device__ __forceinline__ void row_c2r(const float2* X, float2* L, float2* v, int t, bool active,
+                                        const float2* __restrict__ twN,
+                                        const float2* __restrict__ twM) {
+  using C = ZC<N>;
+  constexpr int M = N / 2, T = C::T, E = M / T;
+  for (int k = t; k <= M; k += T) L[k] = active ? X[k] : make_float2(0.f, 0.f);
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int k = t + T * e;
+    float2 xa = L[k], xb = cconj(L[M - k]);
+    if (k == 0) {
+      xa = make_float2(L[0].x, 0.f);
+      xb = make_float2(L[M].x, 0.f);
+    }
+    const float2 s = cadd(xa, xb);
+    const float2 r = cmul(cconj(twN[k]), csub(xa, xb));
+    v[e] = make_float2(s.x - r.y, s.y + r.x);
+  }
+  __syncthreads();
+  fft<M, T, -1>(v, L, 1, t, active, twM, typename C::RL{});
+}
+
+// R2C of v (same distribution) into the half-complex row X.
+template <int N>
+__device__ __forceinline__ void row_r2c(float2* v, float2* L, float2* X, int t, bool active,
+                                        const float2* __restrict__ twN,
+                                        const float2* __restrict__ twM) {
+  using C = ZC<N>;
+  constexpr int M = N / 2, T = C::T, E = M / T;
+  fft<M, T, +1>(v, L, 1, t, active, twM, typename C::RL{});
+  if (active) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) L[t + T * e] = v[e];
+  }
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int k = t + T * e;
+      const float2 zk = L[k];
+      const float2 zc = cconj(L[k == 0 ? 0 : M - k]);
+      const float2 ev = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y + zc.y));
+      const float2 df = csub(zk, zc);
+      const float2 od = make_float2(0.5f * df.y, -0.5f * df.x);
+      X[k] = cadd(ev, cmul(twN[k], od));
+    }
+    if (t == 0) X[M] = make_float2(L[0].x - L[0].y, 0.f);
+  }
+  __syncthreads();
+}
+
+template <int N, int MODE>
+__device__ __forceinline__ void zpass_l(const ChainDev& d, int lt, const ZArgs a,
+                                        const float2* __restrict__ twall, float2* lds,
+                                        double* red) {
+  using C = ZC<N>;
+  constexpr int M = N / 2, T = C::T, B = C::B, E = M / T, H = M + 1, RS = M + 2;
+  const float2* twM = twall + tw_offset(M);
+  const float2* twN = twall + tw_offset(N);
+  const int tid = threadIdx.x, t = tid % T, b = tid / T;
+  const int row = lt * B + b;
+  const bool active = row < N * N;
+  float2* L = lds + b * RS;
+  const size_t roff = (size_t)(active ? row : 0) * H;
+  const size_t rbase = (size_t)(active ? row : 0) * N;
+  const float2* sm = reinterpret_cast<const float2*>(d.smass + rbase);
+  float2 v[E];
+  double sum = 0.0, dat = 0.0;
+  if constexpr (MODE == LZ_FORCE) {
+    float2 w[E];
+    row_c2r<N>(d.T3 + roff, L, w, t, active, twN, twM);  // prior force F^-1(delta_hat/lambda)
+    row_c2r<N>(d.T + roff, L, v, t, active, twN, twM);   // delta
+    float* drout = (a.flags & ZF_WRITE_DRN) ? d.drn : (a.flags & ZF_WRITE_DR) ? d.dr : nullptr;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int n = t + T * e;
+      const float2 x = v[e], fp = w[e];
+      const float2 z2 = make_float2(0.f, 0.f);
+      const float2 al = active ? ld_s(reinterpret_cast<const float2*>(d.alpha + rbase) + n) : z2;
+      const float2 be = active ? ld_s(reinterpret_cast<const float2*>(d.beta + rbase) + n) : z2;
+      const float2 s = active ? sm[n] : z2;
+      if (active && drout) reinterpret_cast<float2*>(drout + rbase)[n] = x;
+      const float g0 = fp.x + al.x * x.x - be.x, g1 = fp.y + al.y * x.y - be.y;
+      if (active) {
+        sum += (double)g0 + (double)g1;
+        if (a.flags & ZF_DATA)
+          dat += (0.5 * al.x * x.x - be.x) * (double)x.x + (0.5 * al.y * x.y - be.y) * (double)x.y;
+      }
+      v[e] = make_float2(s.x * g0, s.y * g1);
+    }
+  } else {
+    row_c2r<N>(d.T2 + roff, L, v, t, active, twN, twM);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const float2 s = active ? sm[t + T * e] : make_float2(0.f, 0.f);
+      v[e] = make_float2(s.x * v[e].x, s.y * v[e].y);
+    }
+  }
+  row_r2c<N>(v, L, (MODE == LZ_FORCE ? d.T : d.T2) + roff, t, active, twN, twM);
+  if constexpr (MODE == LZ_FORCE) {
+    const double s1 = block_sum(sum, red);
+    if (threadIdx.x == 0) d.part[kPartAux * d.maxtiles + lt] = s1;
+    if (a.flags & ZF_DATA) {
+      const double s2 = block_sum(dat, red);
+      if (threadIdx.x == 0) d.part[kPartDat * d.maxtiles + lt] = s2;
+    }
+  }
+  __syncthreads();
+}
+
+template <int N, int MODE>
+__device__ __forceinline__ void xpass_l(const ChainDev& d, int lt, const XArgs a,
+                                        const float2* __restrict__ twall, float2* lds,
+                                        double* red) {
+  using C = XC<N>;
+  constexpr int T = C::T, B = C::B, E = N / T, H = N / 2 + 1, ES = B + 1;
+  const float2* tw = twall + tw_offset(N);
+  const int tid = threadIdx.x, b = tid % B, t = tid / B;
+  const int col = lt * B + b;
+  const bool active = col < N * H;
+  const size_t stride = (size_t)N * H;
+  const int ky = active ? col / H : 0, kz = active ? col % H : 0;
+  const int fy = sfreq(ky, N);
+  const double wz = (kz == 0 || kz == N / 2) ? 1.0 : 2.0;
+  const float norm = d.norm;
+  const float kick = a.kick * d.eps, drift = a.drift * d.eps;
+  constexpr bool KICK = MODE == L_KICK || MODE == L_KICK_LAST;
+  float2* L = lds + b;
+  const float2* src = MODE == L_DRIFT ? d.T2 : d.T;
+  float2 v[E], w[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e)
+    v[e] = active ? src[(size_t)(t + T * e) * stride + col] : make_float2(0.f, 0.f);
+  fft<N, T, +1>(v, L, ES, t, active, tw, typename C::RL{});
+  const float gbar = KICK ? (float)d.P[kGbar] : 0.f;
+  double acc0 = 0.0, acc1 = 0.0;
+  const float2 z2 = make_float2(0.f, 0.f);
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int kx = t + T * e;
+    const int m = shell_of(sfreq(kx, N), fy, kz, N, d.nb);
+    const size_t idx = (size_t)kx * stride + col;
+    const float il = m >= 0 ? d.tf[kTInvLam + m] : 0.f;
+    if constexpr (MODE == L_START) {
+      const float sq = m >= 0 ? d.tf[kTSqrtMass + m] : 0.f;
+      const float2 pk = cscale(v[e], norm * sq);
+      const float2 dk = active && m >= 0 ? ld_s(d.dk + idx) : z2;
+      if (active) {
+        d.bdk[idx] = dk;
+        d.bgk[idx] = d.gk[idx];
+        st_s(d.pk + idx, pk);
+        if (m >= 0) {
+          acc0 += wz * ((double)pk.x * pk.x + (double)pk.y * pk.y) * d.td[kDInvMass + m];
+          acc1 += wz * ((double)dk.x * dk.x + (double)dk.y * dk.y) * d.td[kDInvLam + m];
+        }
+      }
+      v[e] = cscale(dk, norm);
+      w[e] = cscale(dk, norm * il);
+    } else if constexpr (MODE == L_DRIFT) {
+      float2 dk = active && m >= 0 ? ld_s(d.dk + idx) : z2;
+      if (m >= 0) {
+        dk.x += drift * norm * v[e].x;
+        dk.y += drift * norm * v[e].y;
+      }
+      if (active) st_s(d.dk + idx, dk);
+      v[e] = cscale(dk, norm);
+      w[e] = cscale(dk, norm * il);
+    } else {
+      float2 pk = active && m >= 0 ? ld_s(d.pk + idx) : z2;
+      if (m >= 0) {
+        const float2 sh = active ? d.shat[idx] : z2;
+        pk.x -= kick * (norm * v[e].x - gbar * sh.x);
+        pk.y -= kick * (norm * v[e].y - gbar * sh.y);
+      }
+      if (active) st_s(d.pk + idx, pk);
+      if constexpr (MODE == L_KICK_LAST) {
+        if (active && m >= 0) {
+          const float2 dk = ld_s(d.dk + idx);
+          acc0 += wz * ((double)pk.x * pk.x + (double)pk.y * pk.y) * d.td[kDInvMass + m];
+          acc1 += wz * ((double)dk.x * dk.x + (double)dk.y * dk.y) * d.td[kDInvLam + m];
+        }
+      } else {
+        v[e] = m >= 0 ? cscale(pk, norm * d.tf[kTInvMass + m]) : z2;
+      }
+    }
+  }
+  if constexpr (MODE == L_START || MODE == L_DRIFT) {
+    fft<N, T, -1>(v, L, ES, t, active, tw, typename C::RL{});
+    if (active) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) d.T[(size_t)(t + T * e) * stride + col] = v[e];
+    }
+    fft<N, T, -1>(w, L, ES, t, active, tw, typename C::RL{});
+    if (active) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) d.T3[(size_t)(t + T * e) * stride + col] = w[e];
+    }
+  } else if constexpr (MODE == L_KICK) {
+    fft<N, T, -1>(v, L, ES, t, active, tw, typename C::RL{});
+    if (active) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) d.T2[(size_t)(t + T * e) * stride + col] = v[e];
+    }
+  }
+  if constexpr (MODE == L_START || MODE == L_KICK_LAST) {
+    const double s0 = block_sum(0.5 * acc0, red);
+    const double s1 = block_sum(0.5 * acc1, red);
+    if (threadIdx.x == 0) {
+      d.part[kPartKin * d.maxtiles + lt] = s0;
+      d.part[kPartPri * d.maxtiles + lt] = s1;
+    }
+  }
+  __syncthreads();
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(kThreads) k_xpass_l(const ChainDev* __restrict__ ch, int nch,
+                                                       int total, XArgs a,
+                                                       const float2* __restrict__ tw) {
+  extern __shared__ float2 lds[];
+  __shared__ double red[4];
+  for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
+    const ChainDev& d = ch[find_chain(ch, nch, tile, kTileXY)];
+    const int lt = tile - d.tb[kTileXY];
+    switch (d.n) {
+#define C(NN) case NN: xpass_l<NN, MODE>(d, lt, a, tw, lds, red); break;
+      HMC_FOR_N(C)
+#undef C
+      default: break;
+    }
+  }
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(kThreads) k_zpass_l(const ChainDev* __restrict__ ch, int nch,
+                                                       int total, ZArgs a,
+                                                       const float2* __restrict__ tw) {
+  extern __shared__ float2 lds[];
+  __shared__ double red[4];
+  for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
+    const ChainDev& d = ch[find_chain(ch, nch, tile, kTileZ)];
+    const int lt = tile - d.tb[kTileZ];
+    switch (d.n) {
+#define C(NN) case NN: zpass_l<NN, MODE>(d, lt, a, tw, lds, red); break;
+      HMC_FOR_N(C)
+#undef C
+      default: break;
+    }
+  }
+}
+
+// learned-mass factor: phase 0 sums exp(logvar) per tile, phase 1 writes
+// D^(1/2) = sqrt(exp(logvar) / mean(exp(logvar)))
+__global__ void __launch_bounds__(kThreads) k_mass_prep(const ChainDev* __restrict__ ch, int total,
+                                                         const float* __restrict__ lv, int phase) {
+  __shared__ double red[4];
+  const ChainDev& d = ch[0];
+  for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
+    double acc = 0.0;
+    for (int j = threadIdx.x; j < kElemPerTile; j += kThreads) {
+      const long long i = (long long)tile * kElemPerTile + j;
+      if (i >= d.nv) break;
+      if (phase == 0)
+        acc += exp((double)lv[i]);
+      else
+        d.smass[i] = (float)sqrt(exp((double)lv[i]) / d.P[kLmean]);
+    }
+    if (phase == 0) {
+      const double s = block_sum(acc, red);
+      if (threadIdx.x == 0) d.part[kPartAux * d.maxtiles + tile] = s;
+      __syncthreads();
+    }
+  }
+}
+
 // ------------------------------------------------------------------ launches
 static inline int grid_of(int total, int cap) { return total < cap || cap <= 0 ? total : cap; }
 
@@ -590,24 +886,24 @@ void launch_xpass(int mode, const ChainDev* ch, int nch, int total, int lds, XAr
   }
 }
 void launch_ypass(int dir, const ChainDev* ch, int nch, int total, int lds, const float2* tw,
-                  int cap, hipStream_t s, int uniform_n) {
+                  int cap, hipStream_t s, int uniform_n, int buf) {
   dim3 g(grid_of(total, cap)), bl(kThreads);
   switch (uniform_n) {
 #define C(NN)                                                                          \
   case NN:                                                                             \
     if (dir > 0)                                                                       \
-      hipLaunchKernelGGL((k_ypass_n<NN, 1>), g, bl, lds, s, ch, nch, total, tw);       \
+      hipLaunchKernelGGL((k_ypass_n<NN, 1>), g, bl, lds, s, ch, nch, total, tw, buf);  \
     else                                                                               \
-      hipLaunchKernelGGL((k_ypass_n<NN, -1>), g, bl, lds, s, ch, nch, total, tw);      \
+      hipLaunchKernelGGL((k_ypass_n<NN, -1>), g, bl, lds, s, ch, nch, total, tw, buf); \
     return;
     HMC_FOR_N(C)
 #undef C
     default: break;
   }
   if (dir > 0)
-    hipLaunchKernelGGL(k_ypass<1>, g, bl, lds, s, ch, nch, total, tw);
+    hipLaunchKernelGGL(k_ypass<1>, g, bl, lds, s, ch, nch, total, tw, buf);
   else
-    hipLaunchKernelGGL(k_ypass<-1>, g, bl, lds, s, ch, nch, total, tw);
+    hipLaunchKernelGGL(k_ypass<-1>, g, bl, lds, s, ch, nch, total, tw, buf);
 }
 void launch_zpass(int mode, const ChainDev* ch, int nch, int total, int lds, ZArgs a,
                   const float2* tw, int cap, hipStream_t s, int uniform_n) {
@@ -1118,6 +1414,31 @@ __global__ void __launch_bounds__(kThreads) k_rj(const ChainDev* __restrict__ ch
 // ------------------------------------------------------------------ launch wrappers
 static inline int eg(int total) { return total < 4096 ? total : 4096; }
 
+void launch_xpass_learned(int mode, const ChainDev* ch, int nch, int total, int lds, XArgs a,
+                          const float2* tw, int cap, hipStream_t s, int) {
+  dim3 g(grid_of(total, cap)), bl(kThreads);
+  switch (mode) {
+    case L_START: hipLaunchKernelGGL(k_xpass_l<L_START>, g, bl, lds, s, ch, nch, total, a, tw); break;
+    case L_DRIFT: hipLaunchKernelGGL(k_xpass_l<L_DRIFT>, g, bl, lds, s, ch, nch, total, a, tw); break;
+    case L_KICK: hipLaunchKernelGGL(k_xpass_l<L_KICK>, g, bl, lds, s, ch, nch, total, a, tw); break;
+    case L_KICK_LAST:
+      hipLaunchKernelGGL(k_xpass_l<L_KICK_LAST>, g, bl, lds, s, ch, nch, total, a, tw);
+      break;
+  }
+}
+void launch_zpass_learned(int mode, const ChainDev* ch, int nch, int total, int lds, ZArgs a,
+                          const float2* tw, int cap, hipStream_t s, int) {
+  dim3 g(grid_of(total, cap)), bl(kThreads);
+  if (mode == LZ_FORCE)
+    hipLaunchKernelGGL(k_zpass_l<LZ_FORCE>, g, bl, lds, s, ch, nch, total, a, tw);
+  else
+    hipLaunchKernelGGL(k_zpass_l<LZ_VEL>, g, bl, lds, s, ch, nch, total, a, tw);
+}
+void launch_mass_prep(int phase, const ChainDev* ch, int total_r, const float* logvar,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_mass_prep, dim3(eg(total_r)), dim3(kThreads), 0, s, ch, total_r, logvar,
+                     phase);
+}
 void launch_coeff(const ChainDev* ch, int nch, int total, hipStream_t s) {
   hipLaunchKernelGGL(k_coeff, dim3(eg(total)), dim3(kThreads), 0, s, ch, nch, total);
 }

@@ -13,7 +13,11 @@ enum XFlag : int {
   XF_OUT_ALT = 4,   // X_FWD: store g_hat into the backup buffer instead of grad_k
   XF_OUT_DK = 8,    // X_FWD: store into delta_k (forward transform of a real field)
   XF_NOSTORE = 16,  // X_FWD: do not store
+  XF_OUT_SHAT = 32,  // X_FWD: store into the learned-mass transform F(D^(1/2))
 };
+// learned-mass passes
+enum LMode : int { L_START = 0, L_DRIFT = 1, L_KICK = 2, L_KICK_LAST = 3 };
+enum LZMode : int { LZ_FORCE = 0, LZ_VEL = 1 };
 // z-pass modes (real-space side)
 enum ZMode : int { Z_GRAD = 0, Z_NOISE = 1, Z_C2R = 2, Z_R2C = 3 };
 enum ZFlag : int {
@@ -45,7 +49,13 @@ bool supported_n(int n);
 void launch_xpass(int mode, const ChainDev* ch, int nch, int total, int lds, XArgs a,
                   const float2* tw, int grid_cap, hipStream_t s, int uniform_n);
 void launch_ypass(int dir, const ChainDev* ch, int nch, int total, int lds, const float2* tw,
-                  int grid_cap, hipStream_t s, int uniform_n);
+                  int grid_cap, hipStream_t s, int uniform_n, int buf = 0);  // buf: T, T2, T3
+void launch_xpass_learned(int mode, const ChainDev* ch, int nch, int total, int lds, XArgs a,
+                          const float2* tw, int grid_cap, hipStream_t s, int uniform_n);
+void launch_zpass_learned(int mode, const ChainDev* ch, int nch, int total, int lds, ZArgs a,
+                          const float2* tw, int grid_cap, hipStream_t s, int uniform_n);
+void launch_mass_prep(int phase, const ChainDev* ch, int total_r, const float* logvar,
+                      hipStream_t s);
 void launch_zpass(int mode, const ChainDev* ch, int nch, int total, int lds, ZArgs a,
                   const float2* tw, int grid_cap, hipStream_t s, int uniform_n);
 

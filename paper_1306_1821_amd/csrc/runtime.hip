@@ -26,13 +26,14 @@ thread_local std::string g_err = "";
 struct Chain {
   hmc_config cfg;
   hmc_buffers buf;
+  bool learned = false;  // learned mass installed (hmc_set_mass)
   ChainDev dev;          // host copy of the device descriptor
   ChainDev* solo;        // device descriptor with tile bases at zero
   std::vector<double> hp;  // host mirror of the parameter block
 };
 
 struct WsLayout {
-  size_t T, bdk, bgk, drn, part, shpart, mpart, total;
+  size_t T, bdk, bgk, drn, part, shpart, mpart, T2, T3, shat, smass, total;
   int maxtiles;
 };
 
@@ -64,6 +65,11 @@ WsLayout layout(const hmc_config& c) {
   L.part = off; off = align256(off + (size_t)kPartSlots * mt * 8);
   L.shpart = off; off = align256(off + (size_t)mt * c.n_bins * 8);
   L.mpart = off; off = align256(off + (size_t)mt * std::max(3 * c.n_sub, c.n_bins) * 8);
+  // learned mass: two more intermediate grids, F(D^(1/2)) and D^(1/2)
+  L.T2 = off; off = align256(off + nh * 8);
+  L.T3 = off; off = align256(off + nh * 8);
+  L.shat = off; off = align256(off + nh * 8);
+  L.smass = off; off = align256(off + nv * 4);
   L.total = off;
   return L;
 }
@@ -94,6 +100,7 @@ struct hmc_ctx {
   int nsteps = 0;
   int uniform_n = 0;  // N shared by every chain (0 if sizes differ)
   int max_nb = 0, max_sub = 0;
+  bool learned = false;  // every chain runs the learned mass
   // pass timing (hmc_timing)
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
@@ -176,9 +183,21 @@ struct Seq {
                  c->grid_cap, s, un);
     tm.done(s);
   }
-  void y(int dir) {
+  void y(int dir, int buf = 0) {
     Timed tm(c, 1, s);
-    launch_ypass(dir, d, nch, tot[kTileXY], c->lds_x, c->tw, c->grid_cap, s, un);
+    launch_ypass(dir, d, nch, tot[kTileXY], c->lds_x, c->tw, c->grid_cap, s, un, buf);
+    tm.done(s);
+  }
+  void xl(int mode, float kick, float drift) {
+    Timed tm(c, 3, s);
+    launch_xpass_learned(mode, d, nch, tot[kTileXY], c->lds_x, XArgs{kick, drift, 0}, c->tw,
+                         c->grid_cap, s, un);
+    tm.done(s);
+  }
+  void zl(int mode, int flags) {
+    Timed tm(c, 3, s);
+    launch_zpass_learned(mode, d, nch, tot[kTileZ], c->lds_z, ZArgs{flags, 0, nullptr}, c->tw,
+                         c->grid_cap, s, un);
     tm.done(s);
   }
   void z(int mode, int flags, const float* src = nullptr) {
@@ -428,6 +447,10 @@ hmc_status hmc_init_batch(const hmc_config* cfg, const hmc_buffers* buf, int32_t
     d.part = (double*)(w + L.part);
     d.shpart = (double*)(w + L.shpart);
     d.mpart = (double*)(w + L.mpart);
+    d.T2 = (float2*)(w + L.T2);
+    d.T3 = (float2*)(w + L.T3);
+    d.shat = (float2*)(w + L.shat);
+    d.smass = (float*)(w + L.smass);
     if (hipMalloc(&d.P, kPSize * sizeof(double)) != hipSuccess ||
         hipMalloc(&d.tf, kTSize * sizeof(float)) != hipSuccess ||
         hipMalloc(&d.td, kDSize * sizeof(double)) != hipSuccess ||
@@ -499,7 +522,44 @@ hmc_status hmc_init(const hmc_config* cfg, const hmc_buffers* buf, const double*
 // one density trajectory for every chain; results stay on the device
 // one density trajectory for every chain (draw index from the device counter);
 // no host synchronisation, so it can be captured in a graph
+// density trajectory with the learned mass (see the learned-mass passes in
+// kernels.hip); the plain gradient cache is refreshed after the Metropolis test
+static hmc_status run_trajectory_learned(hmc_ctx* c) {
+  Seq q = seq_all(c);
+  const int nch = (int)c->ch.size();
+  auto force = [&](int zflags) {
+    q.y(-1, 0);
+    q.y(-1, 2);
+    q.zl(LZ_FORCE, zflags);
+    launch_reduce_slot(c->d_all, nch, kPartAux, kGbar, kTileZ, c->stream, true);
+    q.y(+1, 0);
+  };
+  q.z(Z_NOISE, 0);
+  q.y(+1);
+  q.xl(L_START, 0.f, 0.f);
+  launch_reduce_slot(c->d_all, nch, kPartKin, kK0, kTileXY, c->stream);
+  launch_reduce_slot(c->d_all, nch, kPartPri, kPi0, kTileXY, c->stream);
+  force(0);
+  q.xl(L_KICK, 0.5f, 0.f);
+  for (int s = 1; s <= c->nsteps; ++s) {
+    const bool last = s == c->nsteps;
+    q.y(-1, 1);
+    q.zl(LZ_VEL, 0);
+    q.y(+1, 1);
+    q.xl(L_DRIFT, 0.f, 1.f);
+    force(last ? (ZF_WRITE_DRN | ZF_DATA) : 0);
+    q.xl(last ? L_KICK_LAST : L_KICK, last ? 0.5f : 1.f, 0.f);
+  }
+  launch_reduce_slot(c->d_all, nch, kPartKin, kK1, kTileXY, c->stream);
+  launch_reduce_slot(c->d_all, nch, kPartPri, kPi1, kTileXY, c->stream);
+  launch_reduce_slot(c->d_all, nch, kPartDat, kD1, kTileZ, c->stream);
+  launch_accept(c->d_all, nch, c->stream);
+  launch_commit(C_HMC, c->d_all, nch, c->total[kTileK], c->total[kTileR], c->stream);
+  return refresh_gradient(c, false);
+}
+
 static hmc_status run_trajectory(hmc_ctx* c) {
+  if (c->learned) return run_trajectory_learned(c);
   Seq q = seq_all(c);
   const int nch = (int)c->ch.size();
   q.z(Z_NOISE, 0);
@@ -776,8 +836,41 @@ hmc_status hmc_timing(hmc_ctx* c, int32_t enable, double* ms, int64_t* launches)
 
 hmc_status hmc_set_mass(hmc_ctx* c, int32_t chain, const float* logvar_dev) {
   if (!c || chain < 0 || chain >= (int)c->ch.size()) return fail(c, HMC_EINVAL, "bad argument");
-  if (logvar_dev == nullptr) return HMC_OK;
-  return fail(c, HMC_EUNSUPPORTED, "learned mass is not built yet");
+  Chain& k = c->ch[chain];
+  if (logvar_dev == nullptr) {
+    k.learned = false;
+  } else {
+    const int tr = k.dev.nt[kTileR], tz = k.dev.nt[kTileZ], tx = k.dev.nt[kTileXY];
+    launch_mass_prep(0, k.solo, tr, logvar_dev, c->stream);
+    launch_reduce_slot(k.solo, 1, kPartAux, kLmean, kTileR, c->stream, true);
+    launch_mass_prep(1, k.solo, tr, logvar_dev, c->stream);
+    // F(D^(1/2)) (unitary, k = 0 entry zeroed) for the mean-removal term of the kick
+    launch_zpass(Z_R2C, k.solo, 1, tz, c->lds_z, ZArgs{0, 0, k.dev.smass}, c->tw, 0, c->stream,
+                 k.cfg.n);
+    launch_ypass(+1, k.solo, 1, tx, c->lds_x, c->tw, 0, c->stream, k.cfg.n);
+    launch_xpass(X_FWD, k.solo, 1, tx, c->lds_x, XArgs{0.f, 0.f, XF_OUT_SHAT}, c->tw, 0,
+                 c->stream, k.cfg.n);
+    hmc_status st = check_launch(c);
+    if (st != HMC_OK) return st;
+    k.learned = true;
+  }
+  bool all = true, any = false;
+  for (auto& kk : c->ch) {
+    all &= kk.learned;
+    any |= kk.learned;
+  }
+  if (any && !all) {
+    c->learned = false;
+    return fail(c, HMC_EUNSUPPORTED,
+                "learned mass set on some chains only; trajectories use the plain mass until "
+                "every chain of the context has one");
+  }
+  c->learned = all;
+  // captured graphs hold the old pass sequence
+  if (c->g_traj) (void)hipGraphExecDestroy(c->g_traj);
+  if (c->g_sweep) (void)hipGraphExecDestroy(c->g_sweep);
+  c->g_traj = c->g_sweep = nullptr;
+  return HMC_OK;
 }
 
 }  // extern "C"

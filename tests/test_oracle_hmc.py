@@ -117,3 +117,89 @@ def test_chain_matches_dense_wiener_posterior():
     var = y.var(axis=0)
     assert np.max(np.abs(var - 1.0) * np.sqrt(ess / 2.0)) < 6.0
     assert abs(var.mean() - 1.0) < 0.03
+
+
+def test_learned_mass_with_unit_D_is_plain_leapfrog():
+    mk, cfg, post, dk = posterior()
+    p = hmc.draw_momentum(post, 6, 0, 0)
+    one = np.ones((cfg.n,) * 3)
+    d1, p1, _, _ = hmc.leapfrog(dk, p, post, 0.1, 7)
+    d2, p2, _ = hmc.leapfrog_learned(dk, p, post, one, 0.1, 7)
+    assert np.max(np.abs(d1 - d2)) < 1e-11 * np.max(np.abs(d1))
+    assert np.max(np.abs(p1 - p2)) < 1e-11 * np.max(np.abs(p1))
+
+
+def test_learned_mass_leapfrog_is_dense_affine_map():
+    """In the variables (delta, pi) with pi = F^-1(p_hat / sqrt(m)) the learned leapfrog is
+    delta' = T pi, pi' = -T^T (Q delta - beta), T = P S C, S = diag(D^(1/2)),
+    C = F^-1 diag(m^-1/2) F: checked against those dense matrices at 8^3."""
+    mk, cfg, post, dk = posterior()
+    n = cfg.n
+    rng = np.random.default_rng(12)
+    sqrtD = hmc.mass_factor(0.5 * rng.standard_normal((n, n, n)))
+    lam_m = model.lambdas(mk["pk_init"], n, cfg.box)
+    _, _, Q, U = dense.wiener(n, lam_m, cfg.nb, post.alpha, post.beta)
+    sh = dense.shell_full(n, cfg.nb)
+    isq = np.where(sh >= 0, 1.0 / np.sqrt(model.mass_table(lam_m, post.abar)[np.maximum(sh, 0)]), 0.0)
+    C = dense.fourier_diag_operator(n, isq)
+    P = U @ U.T
+    T = P @ (sqrtD.reshape(-1)[:, None] * C)
+    beta = post.beta.reshape(-1)
+    pk = hmc.draw_momentum(post, 8, 0, 0)
+    sel = post.shells >= 0
+    eps, steps = 0.1, 6
+    d = grid.inv(dk, n).reshape(-1)
+    pi = grid.inv(np.where(sel, pk / np.sqrt(np.where(sel, post.mass_k, 1.0)), 0.0), n).reshape(-1)
+    pi = pi - 0.5 * eps * T.T @ (Q @ d - beta)
+    for i in range(steps):
+        d = d + eps * T @ pi
+        pi = pi - (eps if i < steps - 1 else 0.5 * eps) * T.T @ (Q @ d - beta)
+    d1, p1, _ = hmc.leapfrog_learned(dk, pk, post, sqrtD, eps, steps)
+    pi1 = grid.inv(np.where(sel, p1 / np.sqrt(np.where(sel, post.mass_k, 1.0)), 0.0), n).reshape(-1)
+    assert np.max(np.abs(grid.inv(d1, n).reshape(-1) - d)) < 1e-10 * np.max(np.abs(d))
+    assert np.max(np.abs(pi1 - pi)) < 1e-10 * np.max(np.abs(pi))
+
+
+@pytest.mark.slow
+def test_learned_mass_chain_matches_dense_wiener_posterior():
+    """The learned-mass HMC targets the same Wiener posterior (8^3, fixed P, b, Nbar)."""
+    mk, cfg, post, dk = posterior()
+    n = cfg.n
+    rng = np.random.default_rng(14)
+    sqrtD = hmc.mass_factor(0.5 * rng.standard_normal((n, n, n)))
+    lam_m = model.lambdas(mk["pk_init"], n, cfg.box)
+    mu, cov, Q, U = dense.wiener(n, lam_m, cfg.nb, post.alpha, post.beta)
+    evals, evecs = np.linalg.eigh(U.T @ cov @ U)
+    W = (U @ evecs) / np.sqrt(evals)
+    dk = grid.fwd(mu.reshape(n, n, n))
+    S, acc = [], 0
+    for t in range(2500):
+        tr = hmc.trajectory_learned(dk, post, sqrtD, 0.15, 6 + (t % 7), 19, 0, t)
+        dk = tr["state"]
+        acc += tr["accepted"]
+        S.append(grid.inv(dk, n).reshape(-1))
+    y = (np.array(S) - mu) @ W
+    assert acc / 2500 > 0.5
+    ess = np.array([_ess(y[:, j]) for j in range(y.shape[1])])
+    zmean = y.mean(axis=0) * np.sqrt(ess)
+    assert np.max(np.abs(zmean)) < 5.0
+    assert abs(np.mean(zmean ** 2) - 1.0) < 0.3
+    assert abs(y.var(axis=0).mean() - 1.0) < 0.04
+
+
+def test_learned_mass_reversible_and_second_order():
+    mk, cfg, post, dk = posterior()
+    rng = np.random.default_rng(13)
+    sqrtD = hmc.mass_factor(0.4 * rng.standard_normal((cfg.n,) * 3))
+    p = hmc.draw_momentum(post, 9, 0, 0)
+    d1, p1, _ = hmc.leapfrog_learned(dk, p, post, sqrtD, 0.1, 10)
+    d2, p2, _ = hmc.leapfrog_learned(d1, -p1, post, sqrtD, 0.1, 10)
+    assert np.max(np.abs(d2 - dk)) < 1e-10 * np.max(np.abs(dk))
+    d0 = grid.inv(dk, cfg.n)
+    H0 = sum(hmc.energies(dk, p, d0, post))
+    errs = []
+    for eps, n in [(0.1, 10), (0.05, 20), (0.025, 40)]:
+        a, b, x = hmc.leapfrog_learned(dk, p, post, sqrtD, eps, n)
+        errs.append(abs(sum(hmc.energies(a, b, x, post)) - H0))
+    slopes = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(np.abs(slopes - 2.0) < 0.15), slopes
