@@ -13,6 +13,12 @@ The JSON line also carries:
                 library's stream during the timed sweeps, against 8 TB/s;
   cpu_baseline  the float64 CPU oracle timed on this host on a bounded sample
                 of the same workload (a few leapfrog steps).
+
+--learned runs the learned warm start / mass comparison instead: the network
+is trained on plain-sampler draws from 64 seeded 128^3 mocks (four subsamples,
+40 shells), applied to the 256^3 survey, and the line reports P(k) ESS/s with
+the learned and the plain mass (4 chains each, equal acceptance) and the
+burn-in lengths of the warm start and of delta = 0.
 """
 import argparse
 import json
@@ -61,6 +67,68 @@ def cpu_baseline(mk, spec, budget_s):
                        f"{spec['n']}^3 workload, scipy.fft workers={workers}, {dt:.1f} s")
 
 
+def learned_main(args):
+    import torch
+    from paper_1306_1821_amd import learned
+    from paper_1306_1821_amd.binding import CNN
+    from synth import CONFIGS, make_mock
+
+    log = lambda m: print(f"[learned] {m}", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    net = CNN(learned.init_params(3))
+    mocks = learned.mock_series(CONFIGS["cfg2"], range(100, 100 + args.mocks))
+    ins, tg, own = learned.make_training_set(net, mocks, per_batch=8, burn=20, samples=31, thin=8,
+                                             eps=0.035, log=log)
+    del mocks
+    t_draws = time.perf_counter() - t0
+    losses = learned.train(net, ins, tg, own, args.train_steps, lr=2e-3, log=log, log_every=1000)
+    t_train = time.perf_counter() - t0 - t_draws
+    del ins, tg
+    torch.cuda.empty_cache()
+    mk = make_mock(CONFIGS["cfg3"], dtype=np.float32)
+    s = learned.start_chains(mk, 1)
+    x = learned.survey_inputs(net, s, 0, mk)
+    s.close()
+    mu, lv = net.forward(x)
+    burn = learned.burn_in_study(mk, mu, lv, sweeps=args.burn_sweeps, eps=(args.eps, args.eps),
+                                 log=log)
+    ess = learned.ess_study(mk, mu, lv, chains=4, burn=100, sweeps=args.steps, eps0=args.eps,
+                            log=log)
+    pl, le = ess["plain"], ess["learned"]
+    value = float(np.median(le["ess_per_s"]))
+    out = {
+        "metric": "P(k) ESS/s learned-mass vs plain at 256^3, same R-hat",
+        "value": value,
+        "unit": "effective P(k) samples/s (median over shells)",
+        "n_gpus": 1, "steps": args.steps, "warmup": 100,
+        "ms_per_step": le["ms_per_sweep"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "cfg5: CNN trained on 128^3 plain-sampler draws "
+                               f"({args.mocks} mocks x 31), applied to the 256^3 survey "
+                               "(L=1500 Mpc/h, 6 subsamples, 60 shells, joint move on); "
+                               "4 chains per mass, warm-started, one step = one sweep"},
+        "plain": {"median_ess_per_s": float(np.median(pl["ess_per_s"])),
+                  "min_ess_per_s": float(pl["ess_per_s"].min()),
+                  "max_rhat": float(pl["rhat"].max()),
+                  "shells_rhat_below_1.01": int((pl["rhat"] < 1.01).sum()),
+                  "eps": pl["eps"], "acceptance": pl["acceptance"],
+                  "ms_per_sweep": pl["ms_per_sweep"]},
+        "learned": {"median_ess_per_s": value, "min_ess_per_s": float(le["ess_per_s"].min()),
+                    "max_rhat": float(le["rhat"].max()),
+                    "shells_rhat_below_1.01": int((le["rhat"] < 1.01).sum()),
+                    "eps": le["eps"], "acceptance": le["acceptance"],
+                    "ms_per_sweep": le["ms_per_sweep"]},
+        "ratio_median_ess_per_s": value / float(np.median(pl["ess_per_s"])),
+        "burn_in_sweeps": {k: {"potential": int(r["burn_pot"]), "ln_P": int(r["burn_logbias"])}
+                           for k, r in burn.items()},
+        "training": {"draws": int(len(own)), "steps": args.train_steps,
+                     "final_loss": float(losses[-200:].mean()), "draw_seconds": t_draws,
+                     "train_seconds": t_train},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -70,12 +138,21 @@ def main():
     ap.add_argument("--eps", type=float, default=0.02)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--learned", action="store_true",
+                    help="learned warm start / mass comparison (steps = measured sweeps per mass)")
+    ap.add_argument("--mocks", type=int, default=64)
+    ap.add_argument("--train-steps", type=int, default=4000)
+    ap.add_argument("--burn-sweeps", type=int, default=300)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the sampler runs on a single MI355X "
               "(chains or slabs would shard across GPUs, which this build does not do)",
               file=sys.stderr)
         sys.exit(2)
+    if args.learned:
+        if args.steps == 20:
+            args.steps = 600
+        return learned_main(args)
     import torch
     from paper_1306_1821_amd.binding import Sampler
 

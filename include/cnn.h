@@ -53,6 +53,13 @@ hmc_status cnn_get_params(cnn_ctx* ctx, float* params);
  * 2 selection); mu, logvar: device [N^3] outputs (either may be NULL). */
 hmc_status cnn_forward(cnn_ctx* ctx, int32_t n, const float* in3, float* mu, float* logvar);
 
+/* Network inputs from the survey: out3 (device [3][N^3]) receives
+ * beta * beta_scale (the data combination beta_i = sum_l b_l (N^l_i - Nbar_l
+ * R^l_i) of the force, normalised by the caller, e.g. 1 / sum_l b_l^2 Nbar_l),
+ * the angular mask and the radial selection (device [N^3] each). */
+hmc_status cnn_features(cnn_ctx* ctx, int32_t n, const float* beta, float beta_scale,
+                        const float* mask, const float* sel, float* out3);
+
 /* Loss and gradients without updating (host outputs; grad may be NULL). */
 hmc_status cnn_gradient(cnn_ctx* ctx, int32_t n, const float* in3, const float* target,
                         float* grad, double* loss);

@@ -157,6 +157,26 @@ hmc_status gibbs_sweep(hmc_ctx* ctx, uint64_t sweep_index, hmc_sweep_stats* out)
  * [N][N][N] float32), e.g. a warm start; the mean is removed. */
 hmc_status hmc_set_state(hmc_ctx* ctx, int32_t chain, const float* delta_r_dev);
 
+/* Warm start from a predicted posterior mean mu and log-variance s (device
+ * [N][N][N] float32 each, e.g. from cnn_forward): the state becomes
+ *   delta = mu + sqrt(exp(s) / sigma^2) xi,   xi = F^-1(sqrt(lambda_k) F w),
+ * w white noise from Philox stream 10 at draw index `draw_index` (low 32 bits),
+ * lambda_k the chain's current prior eigenvalues (k = 0 excluded) and
+ * sigma^2 = N^-3 sum_{k != 0} lambda_k the prior variance per voxel, i.e. a prior
+ * draw rescaled to the predicted variance and shifted to the predicted mean.
+ * Unlike the mean alone (whose power is far below P(k)), such a start keeps the
+ * first P draws of a sweep near their stationary values.  Gradient, real field
+ * and data energy are refreshed as by hmc_set_state.  The mass only affects
+ * efficiency (text after eq. Mass_matrix) and a start near the posterior only
+ * the burn-in (Sec. "Testing burn-in and statistical efficiency"). */
+hmc_status hmc_warm_start(hmc_ctx* ctx, int32_t chain, const float* mu_dev,
+                          const float* logvar_dev, uint64_t draw_index);
+
+/* Change the leapfrog step size eps of chain `chain` (the same eps also steps
+ * the joint (P, delta) move).  Takes effect from the next trajectory or sweep,
+ * also for captured graphs.  HMC_EINVAL unless eps is positive and finite. */
+hmc_status hmc_set_step(hmc_ctx* ctx, int32_t chain, double eps);
+
 /* Replace P (host [n_bins], (Mpc/h)^3), biases and Nbar (host [c]) of a chain;
  * NULL leaves a block unchanged.  Refreshes alpha, beta, mass and gradient. */
 hmc_status hmc_set_params(hmc_ctx* ctx, int32_t chain, const double* pk, const double* bias,
@@ -183,8 +203,10 @@ hmc_status hmc_shell_index(hmc_ctx* ctx, int32_t chain, int16_t* out_dev);
  * T T^T with T = P D^(1/2) F^-1 diag(m_k^-1/2), P the mean projector, i.e.
  * P D^(1/2) F^-1 diag(1/m_k) F D^(1/2) P; D = 1 is the paper's Fourier-diagonal
  * mass.  A step then costs two more real transforms.  NULL restores the plain
- * mass.  Every chain of a context must use the same kind of mass
- * (HMC_EUNSUPPORTED otherwise; trajectories keep the plain mass). */
+ * mass.  chain = -1 applies the field to every chain (all of one grid size).
+ * Every chain of a context must use the same kind of mass: while only some
+ * have a learned one, leapfrog_trajectory and gibbs_sweep return
+ * HMC_EUNSUPPORTED and do nothing. */
 hmc_status hmc_set_mass(hmc_ctx* ctx, int32_t chain, const float* logvar_dev);
 
 /* Graph replay: with enable = 1, leapfrog_trajectory and gibbs_sweep record

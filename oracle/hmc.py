@@ -162,3 +162,28 @@ def trajectory_learned(dk, post, sqrtD, eps, nsteps, seed, chain, traj):
     acc = bool(np.log(u) < -dH)
     return dict(p0=pk0, e0=e0, e1=e1, dH=dH, accepted=acc, log_u=float(np.log(u)),
                 proposal=dk1, p1=pk1, delta1=delta1, state=dk1 if acc else dk)
+
+
+def prior_draw(post, seed, chain, draw):
+    """xi = F^-1(sqrt(lambda_k) F w), w ~ N(0, 1) per voxel from Philox stream 10:
+    a draw from the Gaussian prior S (eq. Wiener_Posterior_psi's first term)."""
+    n = post.n
+    sel = post.shells >= 0
+    w = philox.normals(seed, chain, philox.STREAM_WARM, draw, n ** 3).reshape(n, n, n)
+    wk = grid.fwd(w, post.workers)
+    return grid.inv(np.where(sel, np.sqrt(np.where(sel, post.lam_k, 0.0)) * wk, 0.0), n,
+                    post.workers)
+
+
+def warm_start(mu, logvar, post, seed, chain, draw):
+    """Start state from a predicted posterior mean mu and log-variance s: a prior
+    draw rescaled from the prior variance per voxel sigma^2 = N^-3 sum_{k!=0}
+    lambda_k to exp(s) and shifted by mu.  Returns delta_hat (k = 0 zeroed)."""
+    sel = post.shells >= 0
+    sigma2 = float(np.sum((post.w * np.where(sel, post.lam_k, 0.0))[sel])) / post.n ** 3
+    xi = prior_draw(post, seed, chain, draw)
+    delta = np.asarray(mu, np.float64) + np.sqrt(np.exp(np.asarray(logvar, np.float64)) / sigma2) * xi
+    dk = grid.fwd(delta, post.workers)
+    dk[0, 0, 0] = 0.0
+    return dk
+

@@ -43,9 +43,10 @@ class HmcSweepStats(ctypes.Structure):
 
 EXPORTS = ["hmc_workspace_bytes", "hmc_init", "hmc_init_batch", "leapfrog_trajectory",
            "hamiltonian", "shell_power", "gibbs_sweep", "hmc_set_state", "hmc_set_params",
-           "hmc_set_coefficients", "hmc_get_params", "hmc_shell_index", "hmc_set_mass",
+           "hmc_set_step", "hmc_warm_start", "hmc_set_coefficients", "hmc_get_params", "hmc_shell_index", "hmc_set_mass",
            "hmc_timing", "hmc_use_graph", "hmc_last_error", "hmc_destroy",
            "cnn_param_count", "cnn_create", "cnn_get_params", "cnn_forward", "cnn_gradient",
+           "cnn_features",
            "cnn_train_step", "cnn_last_error", "cnn_destroy"]
 
 _lib = None
@@ -75,6 +76,8 @@ def lib(path=LIB_PATH):
     L.gibbs_sweep.argtypes = [P, U64, ctypes.POINTER(HmcSweepStats)]
     L.hmc_set_state.argtypes = [P, I32, P]
     L.hmc_set_params.argtypes = [P, I32, D, D, D]
+    L.hmc_set_step.argtypes = [P, I32, ctypes.c_double]
+    L.hmc_warm_start.argtypes = [P, I32, P, P, U64]
     L.hmc_set_coefficients.argtypes = [P, I32, P, P]
     L.hmc_get_params.argtypes = [P, I32, D, D, D]
     L.hmc_shell_index.argtypes = [P, I32, P]
@@ -92,6 +95,7 @@ def lib(path=LIB_PATH):
     L.cnn_get_params.argtypes = [P, F]
     L.cnn_forward.argtypes = [P, I32, P, P, P]
     L.cnn_gradient.argtypes = [P, I32, P, P, F, D]
+    L.cnn_features.argtypes = [P, I32, P, ctypes.c_float, P, P, P]
     L.cnn_train_step.argtypes = [P, I32, P, P, ctypes.c_float, D]
     L.cnn_last_error.argtypes = [P]
     L.cnn_last_error.restype = ctypes.c_char_p
@@ -235,13 +239,30 @@ class Sampler:
         return out
 
     def set_state(self, chain, delta_r):
-        x = self.torch.as_tensor(np.asarray(delta_r, dtype=np.float32)).to(self.device).contiguous()
+        x = delta_r if isinstance(delta_r, self.torch.Tensor) else \
+            self.torch.as_tensor(np.asarray(delta_r, dtype=np.float32))
+        x = x.to(self.device, dtype=self.torch.float32).contiguous()
         self._check(self.L.hmc_set_state(self.ctx, chain, ctypes.c_void_p(x.data_ptr())))
+        self.torch.cuda.synchronize(self.device)
+
+    def warm_start(self, chain, mu, logvar, draw_index=0):
+        """delta = mu + sqrt(exp(logvar) / sigma^2) x (prior draw x); see hmc_warm_start."""
+        f = lambda a: (a if isinstance(a, self.torch.Tensor) else
+                       self.torch.as_tensor(np.asarray(a, dtype=np.float32))).to(
+            self.device, dtype=self.torch.float32).contiguous()
+        m, v = f(mu), f(logvar)
+        self._check(self.L.hmc_warm_start(self.ctx, chain, ctypes.c_void_p(m.data_ptr()),
+                                          ctypes.c_void_p(v.data_ptr()), int(draw_index)))
         self.torch.cuda.synchronize(self.device)
 
     def set_params(self, chain, pk=None, bias=None, nbar=None):
         f = lambda a: None if a is None else _dptr(a)
         self._check(self.L.hmc_set_params(self.ctx, chain, f(pk), f(bias), f(nbar)))
+
+    def set_step(self, chain, eps):
+        """Leapfrog step size of one chain (all chains if chain is None)."""
+        for i in (range(len(self.chains)) if chain is None else [chain]):
+            self._check(self.L.hmc_set_step(self.ctx, i, float(eps)))
 
     def set_coefficients(self, chain, alpha, beta):
         a = self.torch.as_tensor(np.asarray(alpha, dtype=np.float32)).to(self.device).contiguous()
@@ -251,7 +272,9 @@ class Sampler:
         self.torch.cuda.synchronize(self.device)
 
     def set_mass(self, chain, logvar=None):
-        """Install the learned mass from a log-variance field (None: plain mass)."""
+        """Install the learned mass from a log-variance field (None: plain mass);
+        chain None: every chain."""
+        chain = -1 if chain is None else chain
         if logvar is None:
             self._check(self.L.hmc_set_mass(self.ctx, chain, None))
             return
@@ -371,6 +394,16 @@ class CNN:
         self._check(self.L.cnn_forward(self.ctx, n, ctypes.c_void_p(x.data_ptr()),
                                        ctypes.c_void_p(mu.data_ptr()), ctypes.c_void_p(lv.data_ptr())))
         return mu, lv
+
+    def features(self, beta, beta_scale, mask, sel):
+        """[3, N, N, N] device input tensor from beta (device), mask and selection."""
+        b, m, s = self._dev(beta), self._dev(mask), self._dev(sel)
+        n = b.shape[-1]
+        out = self.torch.empty((3, n, n, n), dtype=self.torch.float32, device=self.device)
+        self._check(self.L.cnn_features(self.ctx, n, ctypes.c_void_p(b.data_ptr()), float(beta_scale),
+                                        ctypes.c_void_p(m.data_ptr()), ctypes.c_void_p(s.data_ptr()),
+                                        ctypes.c_void_p(out.data_ptr())))
+        return out
 
     def gradient(self, inputs, target):
         x, t = self._dev(inputs), self._dev(target)

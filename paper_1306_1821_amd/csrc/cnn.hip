@@ -63,6 +63,17 @@ __global__ void __launch_bounds__(256) k_input(long long nv, const float* __rest
   }
 }
 
+__global__ void __launch_bounds__(256) k_features(long long nv, const float* __restrict__ beta,
+                                                  float scale, const float* __restrict__ mask,
+                                                  const float* __restrict__ sel,
+                                                  float* __restrict__ out3) {
+  for (long long v = (long long)blockIdx.x * 256 + threadIdx.x; v < nv; v += (long long)gridDim.x * 256) {
+    out3[v] = beta[v] * scale;
+    out3[nv + v] = mask[v];
+    out3[2 * nv + v] = sel[v];
+  }
+}
+
 enum ConvMode : int { C_FWD_GELU = 0, C_FWD_LAST = 1, C_DGRAD = 2 };
 
 // One wave per 16-voxel tile; CS = channel stride of the input (4 or 16).
@@ -472,6 +483,16 @@ hmc_status cnn_forward(cnn_ctx* c, int32_t n, const float* in3, float* mu, float
   if ((st = forward(c, n, in3)) != HMC_OK) return st;
   const long long nv = (long long)n * n * n;
   hipLaunchKernelGGL(k_outputs, dim3(4096), dim3(256), 0, c->stream, nv, c->z[3], mu, logvar);
+  CCHK(c, hipGetLastError());
+  return HMC_OK;
+}
+
+hmc_status cnn_features(cnn_ctx* c, int32_t n, const float* beta, float beta_scale,
+                        const float* mask, const float* sel, float* out3) {
+  if (!c || !beta || !mask || !sel || !out3 || n < 4) return cfail(c, HMC_EINVAL, "bad argument");
+  const long long nv = (long long)n * n * n;
+  hipLaunchKernelGGL(k_features, dim3(4096), dim3(256), 0, c->stream, nv, beta, beta_scale, mask,
+                     sel, out3);
   CCHK(c, hipGetLastError());
   return HMC_OK;
 }

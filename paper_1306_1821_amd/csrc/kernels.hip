@@ -232,6 +232,7 @@ __device__ __forceinline__ void xpass(const ChainDev& d, int lt, const XArgs a, 
       float2 x = active ? d.dk[idx] : make_float2(0.f, 0.f);
       float s = norm;
       if ((a.flags & XF_SCALE) && m >= 0) s *= d.tf[kTScale + m];
+      if ((a.flags & XF_PRIOR) && m >= 0) s *= (float)sqrt(d.P[kLam + m]);
       v[e] = m < 0 ? make_float2(0.f, 0.f) : cscale(x, s);
     } else if constexpr (MODE == X_FWD) {
       float2 g = m < 0 ? make_float2(0.f, 0.f) : cscale(v[e], norm);
@@ -455,11 +456,12 @@ __device__ __forceinline__ void zpass(const ChainDev& d, int lt, const ZArgs a, 
     for (int e = 0; e < E; ++e)
       v[e] = active ? reinterpret_cast<const float2*>(a.src + rbase)[t + T * e]
                     : make_float2(0.f, 0.f);
-  } else {  // Z_NOISE: white noise w_i from Philox stream 3, element = voxel index
+  } else {  // Z_NOISE: white noise w_i from Philox stream 3 (10: warm start), element = voxel index
+    const uint32_t stream = (a.flags & ZF_WARM) ? hmcrng::kWarm : hmcrng::kMomenta;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const uint64_t vox = rbase + 2 * (uint64_t)(t + T * e);
-      const hmcrng::U4 w = hmcrng::block(d.seed, d.chain, hmcrng::kMomenta, *d.draw, 0,
+      const hmcrng::U4 w = hmcrng::block(d.seed, d.chain, stream, *d.draw, 0,
                                          (uint32_t)(vox >> 2));
       double z0, z1;
       if (((vox >> 1) & 1) == 0)
@@ -837,6 +839,29 @@ __global__ void __launch_bounds__(kThreads) k_mass_prep(const ChainDev* __restri
       const double s = block_sum(acc, red);
       if (threadIdx.x == 0) d.part[kPartAux * d.maxtiles + tile] = s;
       __syncthreads();
+    }
+  }
+}
+
+// warm start: drn <- mu + sqrt(v / sigma^2) drn with v = exp(logvar), drn the
+// prior draw F^-1(sqrt(lambda_k) F w) and sigma^2 = (1/N^3) sum_m n_m lambda_m its
+// per-voxel variance
+__global__ void __launch_bounds__(kThreads) k_warm_combine(const ChainDev* __restrict__ ch,
+                                                            int total, const float* __restrict__ mu,
+                                                            const float* __restrict__ lv) {
+  __shared__ double inv_s2;
+  const ChainDev& d = ch[0];
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int m = 0; m < d.nb; ++m) s += d.P[kNmodes + m] * d.P[kLam + m];
+    inv_s2 = (double)d.nv / s;
+  }
+  __syncthreads();
+  for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
+    for (int j = threadIdx.x; j < kElemPerTile; j += kThreads) {
+      const long long i = (long long)tile * kElemPerTile + j;
+      if (i >= d.nv) break;
+      d.drn[i] = (float)(mu[i] + sqrt(exp((double)lv[i]) * inv_s2) * d.drn[i]);
     }
   }
 }
@@ -1438,6 +1463,11 @@ void launch_mass_prep(int phase, const ChainDev* ch, int total_r, const float* l
                       hipStream_t s) {
   hipLaunchKernelGGL(k_mass_prep, dim3(eg(total_r)), dim3(kThreads), 0, s, ch, total_r, logvar,
                      phase);
+}
+void launch_warm_combine(const ChainDev* ch, int total_r, const float* mu, const float* logvar,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_warm_combine, dim3(eg(total_r)), dim3(kThreads), 0, s, ch, total_r, mu,
+                     logvar);
 }
 void launch_coeff(const ChainDev* ch, int nch, int total, hipStream_t s) {
   hipLaunchKernelGGL(k_coeff, dim3(eg(total)), dim3(kThreads), 0, s, ch, nch, total);

@@ -14,6 +14,7 @@ enum XFlag : int {
   XF_OUT_DK = 8,    // X_FWD: store into delta_k (forward transform of a real field)
   XF_NOSTORE = 16,  // X_FWD: do not store
   XF_OUT_SHAT = 32,  // X_FWD: store into the learned-mass transform F(D^(1/2))
+  XF_PRIOR = 64,     // X_INV: scale delta_hat by sqrt(lambda_k) (prior draw)
 };
 // learned-mass passes
 enum LMode : int { L_START = 0, L_DRIFT = 1, L_KICK = 2, L_KICK_LAST = 3 };
@@ -24,6 +25,7 @@ enum ZFlag : int {
   ZF_WRITE_DR = 1,   // store delta to delta_r
   ZF_WRITE_DRN = 2,  // store delta to the proposal buffer
   ZF_DATA = 4,       // accumulate the data energy
+  ZF_WARM = 8,       // Z_NOISE: Philox stream of the warm start instead of the momenta
 };
 
 struct XArgs {
@@ -58,6 +60,8 @@ void launch_mass_prep(int phase, const ChainDev* ch, int total_r, const float* l
                       hipStream_t s);
 void launch_zpass(int mode, const ChainDev* ch, int nch, int total, int lds, ZArgs a,
                   const float2* tw, int grid_cap, hipStream_t s, int uniform_n);
+void launch_warm_combine(const ChainDev* ch, int total_r, const float* mu, const float* logvar,
+                         hipStream_t s);
 
 // elementwise / reductions
 void launch_coeff(const ChainDev* ch, int nch, int total, hipStream_t s);

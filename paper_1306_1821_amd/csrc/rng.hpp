@@ -18,6 +18,7 @@ enum Stream : uint32_t {
   kBias = 7,
   kRjMomenta = 8,
   kRjAccept = 9,
+  kWarm = 10,
 };
 
 struct U4 {

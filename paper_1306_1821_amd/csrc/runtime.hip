@@ -100,7 +100,8 @@ struct hmc_ctx {
   int nsteps = 0;
   int uniform_n = 0;  // N shared by every chain (0 if sizes differ)
   int max_nb = 0, max_sub = 0;
-  bool learned = false;  // every chain runs the learned mass
+  bool learned = false;      // every chain runs the learned mass
+  bool mass_mixed = false;   // some chains only have a learned mass: no trajectories
   // pass timing (hmc_timing)
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
@@ -587,6 +588,8 @@ static hmc_status run_trajectory(hmc_ctx* c) {
 
 hmc_status leapfrog_trajectory(hmc_ctx* c, uint64_t traj_index, double* dH, int32_t* accepted) {
   if (!c) return fail(nullptr, HMC_EINVAL, "null context");
+  if (c->mass_mixed)
+    return fail(c, HMC_EUNSUPPORTED, "learned mass set on some chains of the context only");
   launch_set_draw(c->d_draw, (uint32_t)traj_index, c->stream);
   hmc_status st = c->use_graph ? run_graph(c, &c->g_traj, run_trajectory) : run_trajectory(c);
   if (st != HMC_OK) return st;
@@ -681,6 +684,8 @@ static hmc_status run_sweep(hmc_ctx* c) {
 
 hmc_status gibbs_sweep(hmc_ctx* c, uint64_t sweep_index, hmc_sweep_stats* out) {
   if (!c) return fail(nullptr, HMC_EINVAL, "null context");
+  if (c->mass_mixed)
+    return fail(c, HMC_EUNSUPPORTED, "learned mass set on some chains of the context only");
   launch_set_draw(c->d_draw, (uint32_t)sweep_index, c->stream);
   hmc_status st = c->use_graph ? run_graph(c, &c->g_sweep, run_sweep) : run_sweep(c);
   if (st != HMC_OK) return st;
@@ -735,6 +740,30 @@ hmc_status hmc_set_state(hmc_ctx* c, int32_t chain, const float* delta_r_dev) {
   return check_launch(c);
 }
 
+hmc_status hmc_warm_start(hmc_ctx* c, int32_t chain, const float* mu_dev,
+                          const float* logvar_dev, uint64_t draw_index) {
+  if (!c || !mu_dev || !logvar_dev || chain < 0 || chain >= (int)c->ch.size())
+    return fail(c, HMC_EINVAL, "bad argument");
+  Chain& k = c->ch[chain];
+  const int tz = k.dev.nt[kTileZ], tx = k.dev.nt[kTileXY], tr = k.dev.nt[kTileR];
+  // prior draw xi = F^-1(sqrt(lambda_k) F w) into the proposal buffer
+  launch_set_draw(c->d_draw, (uint32_t)draw_index, c->stream);
+  launch_zpass(Z_NOISE, k.solo, 1, tz, c->lds_z, ZArgs{ZF_WARM, 0, nullptr}, c->tw, 0, c->stream,
+               k.cfg.n);
+  launch_ypass(+1, k.solo, 1, tx, c->lds_x, c->tw, 0, c->stream, k.cfg.n);
+  launch_xpass(X_FWD, k.solo, 1, tx, c->lds_x, XArgs{0.f, 0.f, XF_OUT_DK}, c->tw, 0, c->stream,
+               k.cfg.n);
+  launch_xpass(X_INV, k.solo, 1, tx, c->lds_x, XArgs{0.f, 0.f, XF_PRIOR}, c->tw, 0, c->stream,
+               k.cfg.n);
+  launch_ypass(-1, k.solo, 1, tx, c->lds_x, c->tw, 0, c->stream, k.cfg.n);
+  launch_zpass(Z_C2R, k.solo, 1, tz, c->lds_z, ZArgs{ZF_WRITE_DRN, 0, nullptr}, c->tw, 0,
+               c->stream, k.cfg.n);
+  launch_warm_combine(k.solo, tr, mu_dev, logvar_dev, c->stream);
+  hmc_status st = check_launch(c);
+  if (st != HMC_OK) return st;
+  return hmc_set_state(c, chain, k.dev.drn);
+}
+
 hmc_status hmc_set_params(hmc_ctx* c, int32_t chain, const double* pk, const double* bias,
                           const double* nbar) {
   if (!c || chain < 0 || chain >= (int)c->ch.size()) return fail(c, HMC_EINVAL, "bad argument");
@@ -770,6 +799,18 @@ hmc_status hmc_set_coefficients(hmc_ctx* c, int32_t chain, const float* alpha_de
   launch_reduce_slot(k.solo, 1, kPartAlpha, kAbar, kTileR, c->stream, true);
   launch_tables(k.solo, 1, c->stream);
   return refresh_gradient(c, true);
+}
+
+hmc_status hmc_set_step(hmc_ctx* c, int32_t chain, double eps) {
+  if (!c || chain < 0 || chain >= (int)c->ch.size() || !(eps > 0) || !std::isfinite(eps))
+    return fail(c, HMC_EINVAL, "bad argument");
+  Chain& k = c->ch[chain];
+  k.cfg.eps = eps;
+  k.dev.eps = (float)eps;
+  hmc_status st = upload_desc(c);
+  if (st != HMC_OK) return st;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return HMC_OK;
 }
 
 hmc_status hmc_get_params(hmc_ctx* c, int32_t chain, double* pk, double* bias, double* nbar) {
@@ -834,38 +875,49 @@ hmc_status hmc_timing(hmc_ctx* c, int32_t enable, double* ms, int64_t* launches)
   return HMC_OK;
 }
 
-hmc_status hmc_set_mass(hmc_ctx* c, int32_t chain, const float* logvar_dev) {
-  if (!c || chain < 0 || chain >= (int)c->ch.size()) return fail(c, HMC_EINVAL, "bad argument");
-  Chain& k = c->ch[chain];
+static hmc_status set_mass_one(hmc_ctx* c, Chain& k, const float* logvar_dev) {
   if (logvar_dev == nullptr) {
     k.learned = false;
-  } else {
-    const int tr = k.dev.nt[kTileR], tz = k.dev.nt[kTileZ], tx = k.dev.nt[kTileXY];
-    launch_mass_prep(0, k.solo, tr, logvar_dev, c->stream);
-    launch_reduce_slot(k.solo, 1, kPartAux, kLmean, kTileR, c->stream, true);
-    launch_mass_prep(1, k.solo, tr, logvar_dev, c->stream);
-    // F(D^(1/2)) (unitary, k = 0 entry zeroed) for the mean-removal term of the kick
-    launch_zpass(Z_R2C, k.solo, 1, tz, c->lds_z, ZArgs{0, 0, k.dev.smass}, c->tw, 0, c->stream,
-                 k.cfg.n);
-    launch_ypass(+1, k.solo, 1, tx, c->lds_x, c->tw, 0, c->stream, k.cfg.n);
-    launch_xpass(X_FWD, k.solo, 1, tx, c->lds_x, XArgs{0.f, 0.f, XF_OUT_SHAT}, c->tw, 0,
-                 c->stream, k.cfg.n);
-    hmc_status st = check_launch(c);
+    return HMC_OK;
+  }
+  const int tr = k.dev.nt[kTileR], tz = k.dev.nt[kTileZ], tx = k.dev.nt[kTileXY];
+  launch_mass_prep(0, k.solo, tr, logvar_dev, c->stream);
+  launch_reduce_slot(k.solo, 1, kPartAux, kLmean, kTileR, c->stream, true);
+  launch_mass_prep(1, k.solo, tr, logvar_dev, c->stream);
+  // F(D^(1/2)) (unitary, k = 0 entry zeroed) for the mean-removal term of the kick
+  launch_zpass(Z_R2C, k.solo, 1, tz, c->lds_z, ZArgs{0, 0, k.dev.smass}, c->tw, 0, c->stream,
+               k.cfg.n);
+  launch_ypass(+1, k.solo, 1, tx, c->lds_x, c->tw, 0, c->stream, k.cfg.n);
+  launch_xpass(X_FWD, k.solo, 1, tx, c->lds_x, XArgs{0.f, 0.f, XF_OUT_SHAT}, c->tw, 0,
+               c->stream, k.cfg.n);
+  hmc_status st = check_launch(c);
+  if (st != HMC_OK) return st;
+  k.learned = true;
+  return HMC_OK;
+}
+
+hmc_status hmc_set_mass(hmc_ctx* c, int32_t chain, const float* logvar_dev) {
+  if (!c || chain < -1 || chain >= (int)c->ch.size()) return fail(c, HMC_EINVAL, "bad argument");
+  if (chain >= 0) {
+    hmc_status st = set_mass_one(c, c->ch[chain], logvar_dev);
     if (st != HMC_OK) return st;
-    k.learned = true;
+  } else {
+    for (auto& k : c->ch) {
+      if (logvar_dev && k.cfg.n != c->ch[0].cfg.n)
+        return fail(c, HMC_EINVAL, "chain -1 with a field needs chains of one grid size");
+    }
+    for (auto& k : c->ch) {
+      hmc_status st = set_mass_one(c, k, logvar_dev);
+      if (st != HMC_OK) return st;
+    }
   }
   bool all = true, any = false;
   for (auto& kk : c->ch) {
     all &= kk.learned;
     any |= kk.learned;
   }
-  if (any && !all) {
-    c->learned = false;
-    return fail(c, HMC_EUNSUPPORTED,
-                "learned mass set on some chains only; trajectories use the plain mass until "
-                "every chain of the context has one");
-  }
   c->learned = all;
+  c->mass_mixed = any && !all;
   // captured graphs hold the old pass sequence
   if (c->g_traj) (void)hipGraphExecDestroy(c->g_traj);
   if (c->g_sweep) (void)hipGraphExecDestroy(c->g_sweep);

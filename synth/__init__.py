@@ -5,4 +5,5 @@ with a chosen P(k), a survey response (angular mask times radial selection)
 and mock galaxy counts from the linear data model, all from numpy's seeded
 generators.  Both sides of every parity test receive exactly these arrays.
 """
-from .mock import CONFIGS, MockConfig, make_mock, fiducial_shape, shell_centres  # noqa: F401
+from .mock import (CONFIGS, MockConfig, fiducial_shape, make_mock, mask_and_selection,  # noqa: F401
+                   shell_centres)

@@ -131,6 +131,12 @@ def _directions(n, box):
 
 def response(cfg):
     """R = C(angle) n(r), float64 [N][N][N]."""
+    C, sel = mask_and_selection(cfg)
+    return C * sel
+
+
+def mask_and_selection(cfg):
+    """Angular mask C and radial selection n(r) separately (float64 [N][N][N])."""
     n, box = cfg.n, cfg.box
     x, y, z, r = _directions(n, box)
     cos_t = z / r
@@ -153,19 +159,22 @@ def response(cfg):
             flat[s:s + chunk][dots.max(axis=1) > cmin] = 0.0
     rp = cfg.r_s * (4.0 / 3.0) ** (2.0 / 3.0)
     sel = (r / rp) ** 2 * np.exp(-((r / cfg.r_s) ** 1.5 - (rp / cfg.r_s) ** 1.5))
-    return C * sel
+    return C, sel
 
 
-def make_mock(cfg, dtype=np.float64):
+def make_mock(cfg, dtype=np.float64, geometry=None):
     """Mock survey for `cfg`.  Returns a dict of arrays and scalars.
 
     R, counts: [c][N][N][N]; delta: truth field [N][N][N]; pk_init: prior
-    spectrum at the shell centres, (Mpc/h)^3; A: spectrum amplitude.
+    spectrum at the shell centres, (Mpc/h)^3; A: spectrum amplitude; mask,
+    sel: angular mask and radial selection.  geometry: (mask, sel) computed
+    earlier by mask_and_selection for the same geometry (saves the mask).
     """
     n, box = cfg.n, cfg.box
     A = amplitude(n, box)
     delta = gaussian_field(n, box, A, cfg.seed)
-    R1 = response(cfg)
+    C, sel = mask_and_selection(cfg) if geometry is None else geometry
+    R1 = C * sel
     obs = R1 > 0
     rng = np.random.default_rng(2000 + cfg.seed)
     c = cfg.nsub
@@ -178,5 +187,6 @@ def make_mock(cfg, dtype=np.float64):
         R[l] = R1
     pk_init = A * fiducial_shape(shell_centres(n, box, cfg.nb))
     return dict(cfg=cfg, R=R, counts=counts, delta=delta, pk_init=pk_init, A=A,
+                mask=C.astype(dtype), sel=sel.astype(dtype),
                 bias=np.array(cfg.bias, dtype=np.float64),
                 nbar=np.array(cfg.nbar, dtype=np.float64), n_obs=int(obs.sum()))

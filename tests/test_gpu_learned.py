@@ -55,3 +55,56 @@ def test_learned_trajectory_matches_oracle(case, eps, nsteps):
     ref = hmc.trajectory(before["delta_k"].astype(np.complex128), post, eps, nsteps, 43, 0, 9)
     assert rel_l2(s.state(0)["mom_k"], ref["p1"]) < 1e-4
     s.close()
+
+
+@pytest.mark.parametrize("case", ["small16", "cfg1", 64])
+def test_warm_start_matches_oracle(case):
+    mk = case_mock(case)
+    n = mk["cfg"].n
+    rng = np.random.default_rng(n + 1)
+    mu = (0.3 * rng.standard_normal((n, n, n))).astype(np.float32)
+    lv = (np.log(0.05) + 0.6 * rng.standard_normal((n, n, n))).astype(np.float32)
+    s = Sampler([chain_spec(mk, seed=77, chain_id=3)])
+    a32, b32 = coefficients32(mk)
+    post = oracle_posterior(mk, a32, b32, workers=4)
+    for draw in (0, 5):
+        s.warm_start(0, mu, lv, draw)
+        st = s.state(0)
+        ref = hmc.warm_start(mu.astype(np.float64), lv.astype(np.float64), post, 77, 3, draw)
+        e_k = rel_l2(st["delta_k"], ref)
+        e_r = rel_l2(st["delta_r"], np.fft.irfftn(ref, s=(n, n, n), norm="ortho"))
+        print(f"N={n} draw {draw}: delta_hat rel-L2 {e_k:.2e}, delta rel-L2 {e_r:.2e}")
+        assert e_k < 1e-5 and e_r < 1e-5
+    s.close()
+
+
+def test_trained_network_shortens_burn_in():
+    """End to end at 32^3: plain-sampler draws on 16 seeded mocks train the
+    network with the library's kernels; on a held-out mock the trained network
+    fits held-out draws better than the untrained one, and the warm start from
+    its outputs accepts its first trajectory and reaches the stationary band of
+    the potential (set by a chain started at the truth, itself a posterior draw)
+    sooner than the paper's start delta = 0 (same random numbers)."""
+    import dataclasses
+
+    from paper_1306_1821_amd import learned
+    from paper_1306_1821_amd.binding import CNN
+    from synth import CONFIGS
+
+    cfg = dataclasses.replace(CONFIGS["cfg1"], rj=True)
+    net = CNN(learned.init_params(3))
+    mocks = learned.mock_series(cfg, range(100, 116))
+    ins, tg, own = learned.make_training_set(net, mocks, per_batch=16, burn=10, samples=24, thin=3)
+    hold = learned.mock_series(cfg, [999])
+    ins_h, tg_h, own_h = learned.make_training_set(net, hold, per_batch=1, burn=10, samples=16, thin=3)
+    before = learned.held_out_loss(net, ins_h, tg_h, own_h)
+    learned.train(net, ins, tg, own, 800, lr=3e-3)
+    after = learned.held_out_loss(net, ins_h, tg_h, own_h)
+    print(f"held-out loss: untrained {before:.4f}, trained {after:.4f}")
+    assert after < before - 0.2
+    mu, lv = net.forward(ins_h[0])
+    runs = learned.burn_in_study(hold[0], mu, lv, sweeps=200,
+                                 runs=learned.BURN_RUNS[:2] + learned.BURN_RUNS[3:4], log=print)
+    zero, warm = runs["zero"], runs["warm"]
+    assert warm["first_accept"] == 0
+    assert warm["burn_pot"] + 10 <= zero["burn_pot"]

@@ -203,3 +203,50 @@ def test_learned_mass_reversible_and_second_order():
         errs.append(abs(sum(hmc.energies(a, b, x, post)) - H0))
     slopes = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert np.all(np.abs(slopes - 2.0) < 0.15), slopes
+
+
+def _lam_full(post, n, nb):
+    sh = dense.shell_full(n, nb)
+    lam_m = np.zeros(nb)
+    for m in range(nb):
+        lam_m[m] = post.lam_k[post.shells == m][0]
+    return np.where(sh >= 0, lam_m[np.maximum(sh, 0)], 0.0)
+
+
+def test_prior_draw_covariance_matches_dense_prior():
+    """xi = F^-1(sqrt(lambda) F w) has covariance S = F^H diag(lambda) F (dense)."""
+    mk, cfg, post, _ = posterior("tiny8")
+    n = cfg.n
+    S = dense.fourier_diag_operator(n, _lam_full(post, n, cfg.nb))
+    K = 800
+    X = np.stack([hmc.prior_draw(post, 5, 0, d).reshape(-1) for d in range(K)])
+    C = X.T @ X / K
+    rng = np.random.default_rng(3)
+    x = np.arange(n)
+    wave = np.cos(2 * np.pi * x / n)[:, None, None] * np.ones((n, n, n))
+    e0 = np.zeros(n ** 3)
+    e0[0] = 1.0
+    pair = e0.copy()
+    pair[1] = 1.0
+    for u in [e0, pair, wave.reshape(-1), rng.standard_normal(n ** 3)]:
+        ref = u @ S @ u
+        assert abs(u @ C @ u / ref - 1.0) < 0.2, (u @ C @ u, ref)
+    # per-voxel variance: N^-3 sum_k lambda_k
+    assert abs(np.mean(np.diag(C)) / (np.sum(_lam_full(post, n, cfg.nb)) / n ** 3) - 1) < 0.05
+
+
+def test_warm_start_mean_and_variance():
+    """Over draws, delta has mean mu - mean(mu) and per-voxel variance exp(s)."""
+    mk, cfg, post, _ = posterior("tiny8")
+    n = cfg.n
+    rng = np.random.default_rng(4)
+    mu = 0.3 * rng.standard_normal((n, n, n))
+    lv = np.log(0.05) + 0.6 * rng.standard_normal((n, n, n))
+    K = 800
+    D = np.stack([grid.inv(hmc.warm_start(mu, lv, post, 9, 1, d), n) for d in range(K)])
+    v = np.exp(lv)
+    z = (D.mean(axis=0) - (mu - mu.mean())) / np.sqrt(v / K)
+    assert np.max(np.abs(z)) < 5.0
+    ratio = D.var(axis=0) / v
+    assert abs(ratio.mean() - 1.0) < 0.05
+    assert np.corrcoef(D.var(axis=0).ravel(), v.ravel())[0, 1] > 0.9
