@@ -32,6 +32,26 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_bench_256.md")
+KERNELS_SRC = os.path.join(ROOT, "paper_1306_1821_amd", "csrc", "kernels.hip")
+
+
+def measured_traffic():
+    """HBM bytes per X_STEP launch from the committed FETCH_SIZE / WRITE_SIZE
+    summary, or None when the kernel source has changed since it was taken."""
+    import hashlib
+    import re
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    b = re.search(r"x-step traffic per launch \(bytes\): (\d+)", text)
+    h = re.search(r"kernels.hip sha256: ([0-9a-f]{64})", text)
+    if not b or not h:
+        return None
+    if hashlib.sha256(open(KERNELS_SRC, "rb").read()).hexdigest() != h.group(1):
+        return None
+    return int(b.group(1))
 
 
 def workload_spec(name, eps):
@@ -143,6 +163,9 @@ def main():
     ap.add_argument("--mocks", type=int, default=64)
     ap.add_argument("--train-steps", type=int, default=4000)
     ap.add_argument("--burn-sweeps", type=int, default=300)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="after the run, copy a float32 buffer of this size 3 times (a kernel of "
+                         "known traffic that scales hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the sampler runs on a single MI355X "
@@ -212,7 +235,7 @@ def main():
                                f"{'on' if spec['rj'] else 'off'}; one bench step = one sweep",
                    "eps": spec["eps"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": f"k_xpass_n<{n}, X_STEP>", "avg_ms": avg_ms,
                      "launches": int(launches[0]), "bytes_per_launch": bytes_launch},
         "acceptance": float(np.mean(acc)),
@@ -225,6 +248,15 @@ def main():
     s.close()
     del s
     torch.cuda.empty_cache()
+    if args.copy_probe_mib > 0:
+        nbytes = args.copy_probe_mib << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = nbytes
+        del src, dst
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mk, spec, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -133,6 +133,9 @@ hmc_status hmc_init_batch(const hmc_config* cfg, const hmc_buffers* buf, int32_t
  * HAMILTON2_a with n_leapfrog steps of size eps, Metropolis test of eq.
  * acceptance_rule (accept iff ln u < -dH).  On reject delta_k, grad_k and
  * delta_r are restored; mom_k holds the final momentum of the proposal.
+ * traj_index (low 32 bits) selects the Philox draws (momenta, u): a chain must
+ * not repeat an index (nor use one that a gibbs_sweep used), since the same
+ * momenta from a nearby state retrace part of the earlier move.
  * dH, accepted: host pointers with one entry per chain. */
 hmc_status leapfrog_trajectory(hmc_ctx* ctx, uint64_t traj_index, double* dH, int32_t* accepted);
 
@@ -150,7 +153,9 @@ hmc_status shell_power(hmc_ctx* ctx, int32_t chain, double* sigma, int64_t* n_mo
 
 /* One block sweep (eq. multiblock): density HMC, P | delta, the joint move (if
  * rj_move), Nbar | delta, b, b | delta, Nbar, then alpha, beta, mass and
- * gradient are refreshed.  out: host [n_chains]. */
+ * gradient are refreshed.  sweep_index (low 32 bits) selects every Philox
+ * draw of the sweep; as for trajectories, a chain must not repeat an index.
+ * out: host [n_chains]. */
 hmc_status gibbs_sweep(hmc_ctx* ctx, uint64_t sweep_index, hmc_sweep_stats* out);
 
 /* Replace the density state of chain `chain` with a real field (device
@@ -171,6 +176,19 @@ hmc_status hmc_set_state(hmc_ctx* ctx, int32_t chain, const float* delta_r_dev);
  * the burn-in (Sec. "Testing burn-in and statistical efficiency"). */
 hmc_status hmc_warm_start(hmc_ctx* ctx, int32_t chain, const float* mu_dev,
                           const float* logvar_dev, uint64_t draw_index);
+
+/* Launch shape of a pass class (0: k-space x passes, 1: y passes, 2: real-space
+ * z passes): grid = number of persistent workgroups that walk the tiles (a
+ * multiple of 8 keeps each XCD on a contiguous run of tiles), or 0 for one
+ * workgroup per tile (the default).  Results do not depend on it. */
+hmc_status hmc_set_launch(hmc_ctx* ctx, int32_t pass_class, int32_t grid);
+
+/* Autotuner of the launch shapes: for each pass class, times `reps` launches of
+ * each candidate grid (one workgroup per tile, or 2, 3, 4, 5, 6, 8, 12
+ * workgroups per compute unit) on the context's chains with HIP events and keeps
+ * the fastest; chosen (host [3], may be NULL) receives the grids.  The state
+ * (delta_hat, p_hat, the parameters) is unchanged; captured graphs are dropped. */
+hmc_status hmc_autotune(hmc_ctx* ctx, int32_t reps, int32_t* chosen);
 
 /* Change the leapfrog step size eps of chain `chain` (the same eps also steps
  * the joint (P, delta) move).  Takes effect from the next trajectory or sweep,

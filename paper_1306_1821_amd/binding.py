@@ -43,7 +43,7 @@ class HmcSweepStats(ctypes.Structure):
 
 EXPORTS = ["hmc_workspace_bytes", "hmc_init", "hmc_init_batch", "leapfrog_trajectory",
            "hamiltonian", "shell_power", "gibbs_sweep", "hmc_set_state", "hmc_set_params",
-           "hmc_set_step", "hmc_warm_start", "hmc_set_coefficients", "hmc_get_params", "hmc_shell_index", "hmc_set_mass",
+           "hmc_set_step", "hmc_warm_start", "hmc_set_launch", "hmc_autotune", "hmc_set_coefficients", "hmc_get_params", "hmc_shell_index", "hmc_set_mass",
            "hmc_timing", "hmc_use_graph", "hmc_last_error", "hmc_destroy",
            "cnn_param_count", "cnn_create", "cnn_get_params", "cnn_forward", "cnn_gradient",
            "cnn_features",
@@ -78,6 +78,8 @@ def lib(path=LIB_PATH):
     L.hmc_set_params.argtypes = [P, I32, D, D, D]
     L.hmc_set_step.argtypes = [P, I32, ctypes.c_double]
     L.hmc_warm_start.argtypes = [P, I32, P, P, U64]
+    L.hmc_set_launch.argtypes = [P, I32, I32]
+    L.hmc_autotune.argtypes = [P, I32, ctypes.POINTER(I32)]
     L.hmc_set_coefficients.argtypes = [P, I32, P, P]
     L.hmc_get_params.argtypes = [P, I32, D, D, D]
     L.hmc_shell_index.argtypes = [P, I32, P]
@@ -297,6 +299,16 @@ class Sampler:
         out = self.torch.empty((n, n, n // 2 + 1), dtype=self.torch.int16, device=self.device)
         self._check(self.L.hmc_shell_index(self.ctx, chain, ctypes.c_void_p(out.data_ptr())))
         return out.cpu().numpy()
+
+    def set_launch(self, pass_class, grid):
+        """Persistent workgroups for a pass class (0 x, 1 y, 2 z); 0: one per tile."""
+        self._check(self.L.hmc_set_launch(self.ctx, int(pass_class), int(grid)))
+
+    def autotune(self, reps=10):
+        """Pick the fastest launch grid per pass class; returns the three grids."""
+        out = (ctypes.c_int32 * 3)()
+        self._check(self.L.hmc_autotune(self.ctx, int(reps), out))
+        return list(out)
 
     def use_graph(self, enable=True):
         """Replay trajectories / sweeps from captured HIP graphs."""

@@ -99,6 +99,7 @@ struct ChainDev {
   float2* T3;
   float2* shat;
   float* smass;
+  signed char* lut;  // shell index of every q = |k|^2 in grid units (-1 at q = 0)
 };
 
 // Twiddle tables W_L^i = exp(-2 pi i i / L), float2, for every supported

@@ -21,11 +21,22 @@
 #ifndef HMC_NT
 #define HMC_NT 1
 #endif
-#ifndef HMC_PREFETCH
-#define HMC_PREFETCH 0
+// non-temporal hints on the state in the k-space pass (HMC_XNT) and on alpha,
+// beta in the real-space pass (HMC_NT)
+#ifndef HMC_ZPRE
+#define HMC_ZPRE 1
 #endif
-#ifndef HMC_CFG256
-#define HMC_CFG256 1
+#ifndef HMC_XNT
+#define HMC_XNT 0
+#endif
+// 256^3 pencil shapes (threads per pencil T, pencils per block B, radices):
+// HMC_XCFG256 for the x and y passes, HMC_ZCFG256 for the z pass (measured
+// alternatives kept selectable at build time)
+#ifndef HMC_XCFG256
+#define HMC_XCFG256 0
+#endif
+#ifndef HMC_ZCFG256
+#define HMC_ZCFG256 1
 #endif
 #ifndef HMC_XCD
 #define HMC_XCD 1
@@ -34,16 +45,31 @@
 namespace hmc {
 using namespace hmcfft;
 
-// Loads/stores of the streamed state (delta_hat, p_hat, alpha, beta): with
-// HMC_NT they carry the non-temporal hint so that they do not displace the
-// intermediate grid from the caches.
+// Global-memory accesses.  Device pointers taken from the chain descriptor are
+// generic to the compiler, which then emits flat instructions (counted by both
+// the vector-memory and the LDS wait counters, so waits serialise); the casts to
+// the global address space give global loads and stores.  The streamed state
+// (delta_hat, p_hat, alpha, beta) carries the non-temporal hint (HMC_NT) so that
+// it does not displace the intermediate grid from the caches.
 typedef float f2v __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) f2v gf2v;
+typedef __attribute__((address_space(1))) const signed char gschar;
+__device__ __forceinline__ float2 gld(const float2* p) {
+  const f2v v = *(const gf2v*)p;
+  return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void gst(float2* p, float2 v) {
+  f2v w;
+  w.x = v.x;
+  w.y = v.y;
+  *(gf2v*)p = w;
+}
 __device__ __forceinline__ float2 ld_s(const float2* p) {
 #if HMC_NT
-  const f2v v = __builtin_nontemporal_load(reinterpret_cast<const f2v*>(p));
+  const f2v v = __builtin_nontemporal_load((const gf2v*)p);
   return make_float2(v.x, v.y);
 #else
-  return *p;
+  return gld(p);
 #endif
 }
 __device__ __forceinline__ void st_s(float2* p, float2 v) {
@@ -51,10 +77,66 @@ __device__ __forceinline__ void st_s(float2* p, float2 v) {
   f2v w;
   w.x = v.x;
   w.y = v.y;
-  __builtin_nontemporal_store(w, reinterpret_cast<f2v*>(p));
+  __builtin_nontemporal_store(w, (gf2v*)p);
 #else
-  *p = v;
+  gst(p, v);
 #endif
+}
+// uniform base + 32-bit element offset: the byte offset is formed in 32 bits (every
+// array of one chain is below 4 GiB), which lets the compiler use the
+// scalar-base + 32-bit vector-offset form instead of a 64-bit address per element
+typedef __attribute__((address_space(1))) char gchar;
+__device__ __forceinline__ float2 gldi(const float2* base, uint32_t i) {
+  const f2v v = *(const gf2v*)((const gchar*)base + i * 8u);
+  return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void gsti(float2* base, uint32_t i, float2 v) {
+  f2v w;
+  w.x = v.x;
+  w.y = v.y;
+  *(gf2v*)((gchar*)base + i * 8u) = w;
+}
+__device__ __forceinline__ float2 ld_si(const float2* base, uint32_t i) {
+#if HMC_NT
+  const f2v v = __builtin_nontemporal_load((const gf2v*)((const gchar*)base + i * 8u));
+  return make_float2(v.x, v.y);
+#else
+  return gldi(base, i);
+#endif
+}
+__device__ __forceinline__ void st_si(float2* base, uint32_t i, float2 v) {
+#if HMC_NT
+  f2v w;
+  w.x = v.x;
+  w.y = v.y;
+  __builtin_nontemporal_store(w, (gf2v*)((gchar*)base + i * 8u));
+#else
+  gsti(base, i, v);
+#endif
+}
+__device__ __forceinline__ float gldf(const float* p) {
+  return *(const __attribute__((address_space(1))) float*)p;
+}
+__device__ __forceinline__ double gldd(const double* p) {
+  return *(const __attribute__((address_space(1))) double*)p;
+}
+__device__ __forceinline__ float2 xld(const float2* base, uint32_t i) {
+#if HMC_XNT
+  return ld_si(base, i);
+#else
+  return gldi(base, i);
+#endif
+}
+__device__ __forceinline__ void xst(float2* base, uint32_t i, float2 v) {
+#if HMC_XNT
+  st_si(base, i, v);
+#else
+  gsti(base, i, v);
+#endif
+}
+// shell of a mode from the chain's q -> shell table (q = |k|^2 in grid units)
+__device__ __forceinline__ int shell_lut(const signed char* lut, int q) {
+  return (int)*(gschar*)(lut + q);
 }
 
 // ------------------------------------------------------------------ configs
@@ -66,8 +148,10 @@ template <> struct XC<32>  { static constexpr int T = 4,  B = 64;  using RL = Ra
 template <> struct XC<64>  { static constexpr int T = 8,  B = 32;  using RL = Radices<8, 8>; };
 template <> struct XC<128> { static constexpr int T = 8,  B = 32;  using RL = Radices<16, 8>; };
 template <> struct XC<192> { static constexpr int T = 16, B = 16;  using RL = Radices<4, 4, 12>; };
-#if HMC_CFG256 == 1
+#if HMC_XCFG256 == 1
 template <> struct XC<256> { static constexpr int T = 32, B = 8;   using RL = Radices<8, 8, 4>; };
+#elif HMC_XCFG256 == 2
+template <> struct XC<256> { static constexpr int T = 64, B = 4;   using RL = Radices<4, 4, 4, 4>; };
 #else
 template <> struct XC<256> { static constexpr int T = 16, B = 16;  using RL = Radices<16, 16>; };
 #endif
@@ -79,8 +163,10 @@ template <> struct ZC<32>  { static constexpr int T = 4, B = 64;  using RL = Rad
 template <> struct ZC<64>  { static constexpr int T = 4, B = 64;  using RL = Radices<8, 4>; };
 template <> struct ZC<128> { static constexpr int T = 8, B = 32;  using RL = Radices<8, 8>; };
 template <> struct ZC<192> { static constexpr int T = 8, B = 32;  using RL = Radices<4, 4, 6>; };
-#if HMC_CFG256 == 1
+#if HMC_ZCFG256 == 1
 template <> struct ZC<256> { static constexpr int T = 16, B = 16; using RL = Radices<8, 4, 4>; };
+#elif HMC_ZCFG256 == 2
+template <> struct ZC<256> { static constexpr int T = 32, B = 8;  using RL = Radices<4, 4, 4, 2>; };
 #else
 template <> struct ZC<256> { static constexpr int T = 8, B = 32;  using RL = Radices<16, 8>; };
 #endif
@@ -141,10 +227,34 @@ __device__ __forceinline__ int tile_of(int b, int g) {
 #endif
 }
 
-// Shell of a mode with signed integer frequencies: the m with
-// m^2 q_max < nb^2 q <= (m+1)^2 q_max, q_max = 3 (n/2)^2; -1 for q = 0.
-__device__ __forceinline__ int shell_of(int fx, int fy, int fz, int n, int nb) {
-  const uint64_t q = (uint64_t)(fx * fx + fy * fy + fz * fz);
+// Tiles a workgroup processes.  A grid with one workgroup per tile takes the
+// XCD-aware order of tile_of.  A smaller (persistent) grid that is a multiple of 8
+// walks, on each XCD, that XCD's contiguous run of tiles (workgroups are dealt to
+// the 8 XCDs round-robin), so neighbouring tiles still share an L2; any other grid
+// strides over all tiles.
+struct TileWalk {
+  int cur, end, step;
+};
+__device__ __forceinline__ TileWalk tile_walk(int total) {
+  const int g = gridDim.x, b = blockIdx.x;
+#if HMC_XCD
+  if (g == total) {
+    const int t = tile_of(b, total);
+    return {t, t + 1, 1};
+  }
+  if ((g & 7) == 0 && g < total) {
+    const int q = total >> 3, r = total & 7, x = b & 7, i = b >> 3;
+    const int lo = x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q;
+    return {lo + i, lo + q + (x < r ? 1 : 0), g >> 3};
+  }
+#endif
+  return {b, total, g};
+}
+
+// Shell of a mode: the m with m^2 q_max < nb^2 q <= (m+1)^2 q_max,
+// q = |k|^2 in grid units, q_max = 3 (n/2)^2; -1 for q = 0.  Evaluated once per
+// q into the chain's table (k_shell_lut); the passes look it up.
+__device__ __forceinline__ int shell_q(uint64_t q, int n, int nb) {
   if (q == 0) return -1;
   const uint64_t qmax = 3ull * (uint64_t)(n / 2) * (uint64_t)(n / 2);
   const uint64_t lhs = (uint64_t)nb * (uint64_t)nb * q;
@@ -153,6 +263,9 @@ __device__ __forceinline__ int shell_of(int fx, int fy, int fz, int n, int nb) {
   while ((uint64_t)t * (uint64_t)t * qmax < lhs) ++t;
   while (t > 1 && (uint64_t)(t - 1) * (uint64_t)(t - 1) * qmax >= lhs) --t;
   return t - 1;
+}
+__device__ __forceinline__ int shell_of(const ChainDev& d, int fx, int fy, int fz) {
+  return shell_lut(d.lut, fx * fx + fy * fy + fz * fz);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -184,103 +297,119 @@ __device__ __forceinline__ void bins_flush(double* bins, double* dst, int nb) {
 }
 
 // ------------------------------------------------------------------ x pass
+// Thread (t, b) of a block holds elements kx = t + T e (e < E) of mode column
+// col = tile B + b (ky = col / H, kz = col % H).  Idle lanes of the last tile read
+// column 0 (in bounds) and store nothing.  Every load of an element is issued
+// before its first use so that one wait covers them.
 template <int N, int MODE>
 __device__ __forceinline__ void xpass(const ChainDev& d, int lt, const XArgs a, const float2* __restrict__ twall,
                       float2* lds, double* red, double* bins) {
   using C = XC<N>;
   constexpr int T = C::T, B = C::B, E = N / T, H = N / 2 + 1, ES = B + 1;
+  constexpr uint32_t stride = (uint32_t)N * H;
   const float2* tw = twall + tw_offset(N);
   const int tid = threadIdx.x, b = tid % B, t = tid / B;
   const int col = lt * B + b;
   const bool active = col < N * H;
-  const size_t stride = (size_t)N * H;
-  const int ky = active ? col / H : 0, kz = active ? col % H : 0;
+  const uint32_t colc = active ? col : 0;
+  const int ky = colc / H, kz = colc % H;
   const int fy = sfreq(ky, N);
+  const int q0 = fy * fy + kz * kz;
   const double wz = (kz == 0 || kz == N / 2) ? 1.0 : 2.0;
   const float norm = d.norm;
   const float kick = a.kick * d.eps, drift = a.drift * d.eps;
+  float2* const Tb = d.T;
+  float2* const dkb = d.dk;
+  float2* const pkb = d.pk;
+  float2* const gkb = d.gk;
+  const signed char* const lut = d.lut;
+  const float* const tf = d.tf;
+  const double* const td = d.td;
   float2* L = lds + b;
   float2 v[E];
+  auto offs = [&](int e) { return colc + (uint32_t)(t + T * e) * stride; };
+  auto shell = [&](int e) {
+    const int fx = sfreq(t + T * e, N);
+    return shell_lut(lut, q0 + fx * fx);
+  };
 
   const bool dot = (MODE == X_FWD) && (a.flags & XF_DOT);
   if (dot) bins_zero(bins);
 
-  constexpr bool pre = HMC_PREFETCH && MODE == X_STEP;
-  float2 pdk[pre ? E : 1], ppk[pre ? E : 1];
-  if constexpr (pre) {
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const size_t idx = (size_t)(t + T * e) * stride + col;
-      pdk[e] = active ? ld_s(d.dk + idx) : make_float2(0.f, 0.f);
-      ppk[e] = active ? ld_s(d.pk + idx) : make_float2(0.f, 0.f);
-    }
-  }
   if constexpr (MODE != X_INV) {
 #pragma unroll
-    for (int e = 0; e < E; ++e)
-      v[e] = active ? d.T[(size_t)(t + T * e) * stride + col] : make_float2(0.f, 0.f);
+    for (int e = 0; e < E; ++e) v[e] = gldi(Tb, offs(e));
     fft<N, T, +1>(v, L, ES, t, active, tw, typename C::RL{});
   }
 
   double acc0 = 0.0, acc1 = 0.0;
+  if constexpr (MODE == X_INV) {
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int kx = t + T * e;
-    const int m = shell_of(sfreq(kx, N), fy, kz, N, d.nb);
-    const size_t idx = (size_t)kx * stride + col;
-    if constexpr (MODE == X_INV) {
-      float2 x = active ? d.dk[idx] : make_float2(0.f, 0.f);
+    for (int e = 0; e < E; ++e) {
+      const int me = shell(e);
+      const float2 x = gldi(dkb, offs(e));
       float s = norm;
-      if ((a.flags & XF_SCALE) && m >= 0) s *= d.tf[kTScale + m];
-      if ((a.flags & XF_PRIOR) && m >= 0) s *= (float)sqrt(d.P[kLam + m]);
-      v[e] = m < 0 ? make_float2(0.f, 0.f) : cscale(x, s);
-    } else if constexpr (MODE == X_FWD) {
-      float2 g = m < 0 ? make_float2(0.f, 0.f) : cscale(v[e], norm);
+      if ((a.flags & XF_SCALE) && me >= 0) s *= gldf(tf + kTScale + me);
+      if ((a.flags & XF_PRIOR) && me >= 0) s *= (float)sqrt(gldd(d.P + kLam + me));
+      v[e] = me < 0 ? make_float2(0.f, 0.f) : cscale(x, s);
+    }
+  } else if constexpr (MODE == X_FWD) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int me = shell(e);
+      const float2 g = me < 0 ? make_float2(0.f, 0.f) : cscale(v[e], norm);
       if (active && !(a.flags & XF_NOSTORE)) {
         float2* out = (a.flags & XF_OUT_DK)     ? d.dk
                       : (a.flags & XF_OUT_ALT)  ? d.bgk
                       : (a.flags & XF_OUT_SHAT) ? d.shat
                                                 : d.gk;
-        out[idx] = g;
+        gsti(out, offs(e), g);
       }
-      if (dot && active && m >= 0) {
-        float2 x = d.dk[idx];
-        const float s = (a.flags & XF_SCALE) ? d.tf[kTScale + m] : 1.f;
+      if (dot && active && me >= 0) {
+        const float2 x = gldi(dkb, offs(e));
+        const float s = (a.flags & XF_SCALE) ? gldf(tf + kTScale + me) : 1.f;
         const double val = wz * ((double)(s * x.x) * g.x + (double)(s * x.y) * g.y);
-        atomicAdd(&bins[(threadIdx.x >> 6) * kMaxBins + m], val);
+        atomicAdd(&bins[(threadIdx.x >> 6) * kMaxBins + me], val);
       }
-    } else {
-      // X_START, X_STEP, X_END: kick (and drift)
-      float2 dk = make_float2(0.f, 0.f), pk = make_float2(0.f, 0.f), g;
-      if constexpr (pre) {
-        dk = pdk[e];
-        pk = ppk[e];
-      } else if (active) {
-        dk = ld_s(d.dk + idx);
-      }
+    }
+  } else {
+    // X_START, X_STEP, X_END: kick (and drift).  All loads of the elements are
+    // issued before the first use.
+    float2 dkv[E], pkv[E];
+    int m[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      m[e] = shell(e);
+      dkv[e] = xld(dkb, offs(e));
+      pkv[e] = MODE == X_START ? gldi(gkb, offs(e)) : xld(pkb, offs(e));  // X_START: g_hat
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int me = m[e];
+      const float il = me >= 0 ? gldf(tf + kTInvLam + me) : 0.f;
+      const float im = me >= 0 ? gldf(tf + kTInvMass + me) : 0.f;
+      float2 dk = dkv[e], pk, g;
       if constexpr (MODE == X_START) {
         // fresh momentum p_hat = sqrt(m_k) F w; gradient of the current state from memory
-        const float sq = m >= 0 ? d.tf[kTSqrtMass + m] : 0.f;
+        const float sq = me >= 0 ? gldf(tf + kTSqrtMass + me) : 0.f;
         pk = cscale(v[e], norm * sq);
-        g = active ? d.gk[idx] : make_float2(0.f, 0.f);
+        g = pkv[e];
         if (active) {
-          d.bdk[idx] = dk;
-          d.bgk[idx] = g;
+          gsti(d.bdk, offs(e), dk);
+          gsti(d.bgk, offs(e), g);
         }
-        if (active && m >= 0) {
-          acc0 += wz * ((double)pk.x * pk.x + (double)pk.y * pk.y) * d.td[kDInvMass + m];
-          acc1 += wz * ((double)dk.x * dk.x + (double)dk.y * dk.y) * d.td[kDInvLam + m];
+        if (active && me >= 0) {
+          acc0 += wz * ((double)pk.x * pk.x + (double)pk.y * pk.y) * gldd(td + kDInvMass + me);
+          acc1 += wz * ((double)dk.x * dk.x + (double)dk.y * dk.y) * gldd(td + kDInvLam + me);
         }
       } else {
         g = cscale(v[e], norm);
-        if (!pre && active) pk = ld_s(d.pk + idx);
+        pk = pkv[e];
       }
-      if (m >= 0) {
-        const float il = d.tf[kTInvLam + m];
+      if (me >= 0) {
         pk.x -= kick * (dk.x * il + g.x);
         pk.y -= kick * (dk.y * il + g.y);
         if constexpr (MODE != X_END) {
-          const float im = d.tf[kTInvMass + m];
           dk.x += drift * pk.x * im;
           dk.y += drift * pk.y * im;
         }
@@ -289,18 +418,18 @@ __device__ __forceinline__ void xpass(const ChainDev& d, int lt, const XArgs a, 
         dk = make_float2(0.f, 0.f);
       }
       if constexpr (MODE == X_END) {
-        if (active && m >= 0) {
-          acc0 += wz * ((double)pk.x * pk.x + (double)pk.y * pk.y) * d.td[kDInvMass + m];
-          acc1 += wz * ((double)dk.x * dk.x + (double)dk.y * dk.y) * d.td[kDInvLam + m];
+        if (active && me >= 0) {
+          acc0 += wz * ((double)pk.x * pk.x + (double)pk.y * pk.y) * gldd(td + kDInvMass + me);
+          acc1 += wz * ((double)dk.x * dk.x + (double)dk.y * dk.y) * gldd(td + kDInvLam + me);
         }
         if (active) {
-          d.pk[idx] = pk;
-          d.gk[idx] = m < 0 ? make_float2(0.f, 0.f) : g;
+          gsti(pkb, offs(e), pk);
+          gsti(gkb, offs(e), me < 0 ? make_float2(0.f, 0.f) : g);
         }
       } else {
         if (active) {
-          st_s(d.dk + idx, dk);
-          st_s(d.pk + idx, pk);
+          xst(dkb, offs(e), dk);
+          xst(pkb, offs(e), pk);
         }
         v[e] = cscale(dk, norm);
       }
@@ -311,7 +440,7 @@ __device__ __forceinline__ void xpass(const ChainDev& d, int lt, const XArgs a, 
     fft<N, T, -1>(v, L, ES, t, active, tw, typename C::RL{});
     if (active) {
 #pragma unroll
-      for (int e = 0; e < E; ++e) d.T[(size_t)(t + T * e) * stride + col] = v[e];
+      for (int e = 0; e < E; ++e) gsti(Tb, offs(e), v[e]);
     }
   }
   if constexpr (MODE == X_START || MODE == X_END) {
@@ -333,7 +462,8 @@ __global__ void __launch_bounds__(kThreads) k_xpass(const ChainDev* __restrict__
   extern __shared__ float2 lds[];
   __shared__ double red[4];
   __shared__ double bins[4 * kMaxBins];
-  for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
+  for (TileWalk w = tile_walk(total); w.cur < w.end; w.cur += w.step) {
+    const int tile = w.cur;
     const int c = find_chain(ch, nch, tile, kTileXY);
     const ChainDev& d = ch[c];
     const int lt = tile - d.tb[kTileXY];
@@ -354,8 +484,8 @@ __global__ void __launch_bounds__(kThreads) k_xpass_n(const ChainDev* __restrict
   extern __shared__ float2 lds[];
   __shared__ double red[4];
   __shared__ double bins[4 * kMaxBins];
-  for (int b = blockIdx.x; b < total; b += gridDim.x) {
-    const int tile = gridDim.x == total ? tile_of(b, total) : b;
+  for (TileWalk w = tile_walk(total); w.cur < w.end; w.cur += w.step) {
+    const int tile = w.cur;
     const int c = find_chain(ch, nch, tile, kTileXY);
     const ChainDev& d = ch[c];
     xpass<N, MODE>(d, tile - d.tb[kTileXY], a, tw, lds, red, bins);
@@ -372,15 +502,16 @@ __device__ __forceinline__ void ypass(const ChainDev& d, int lt, const float2* _
   const int tid = threadIdx.x, b = tid % B, t = tid / B;
   const int p = lt * B + b;
   const bool active = p < N * H;
-  const int x = active ? p / H : 0, kz = active ? p % H : 0;
-  float2* base = (buf == 0 ? d.T : buf == 1 ? d.T2 : d.T3) + (size_t)x * N * H + kz;
+  const uint32_t x = active ? p / H : 0, kz = active ? p % H : 0;
+  float2* const base = buf == 0 ? d.T : buf == 1 ? d.T2 : d.T3;
+  const uint32_t o0 = x * (uint32_t)(N * H) + kz;  // idle lanes: column 0
   float2 v[E];
 #pragma unroll
-  for (int e = 0; e < E; ++e) v[e] = active ? base[(size_t)(t + T * e) * H] : make_float2(0.f, 0.f);
+  for (int e = 0; e < E; ++e) v[e] = gldi(base, o0 + (uint32_t)((t + T * e) * H));
   fft<N, T, DIR>(v, lds + b, ES, t, active, tw, typename C::RL{});
   if (active) {
 #pragma unroll
-    for (int e = 0; e < E; ++e) base[(size_t)(t + T * e) * H] = v[e];
+    for (int e = 0; e < E; ++e) gsti(base, o0 + (uint32_t)((t + T * e) * H), v[e]);
   }
 }
 
@@ -389,7 +520,8 @@ __global__ void __launch_bounds__(kThreads) k_ypass(const ChainDev* __restrict__
                                                      int total, const float2* __restrict__ tw,
                                                      int buf) {
   extern __shared__ float2 lds[];
-  for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
+  for (TileWalk w = tile_walk(total); w.cur < w.end; w.cur += w.step) {
+    const int tile = w.cur;
     const int c = find_chain(ch, nch, tile, kTileXY);
     const ChainDev& d = ch[c];
     const int lt = tile - d.tb[kTileXY];
@@ -407,8 +539,8 @@ __global__ void __launch_bounds__(kThreads) k_ypass_n(const ChainDev* __restrict
                                                        int total, const float2* __restrict__ tw,
                                                        int buf) {
   extern __shared__ float2 lds[];
-  for (int b = blockIdx.x; b < total; b += gridDim.x) {
-    const int tile = gridDim.x == total ? tile_of(b, total) : b;
+  for (TileWalk w = tile_walk(total); w.cur < w.end; w.cur += w.step) {
+    const int tile = w.cur;
     const int c = find_chain(ch, nch, tile, kTileXY);
     const ChainDev& d = ch[c];
     ypass<N, DIR>(d, tile - d.tb[kTileXY], tw, lds, buf);
@@ -427,13 +559,38 @@ __device__ __forceinline__ void zpass(const ChainDev& d, int lt, const ZArgs a, 
   const int row = lt * B + b;
   const bool active = row < N * N;
   float2* L = lds + b * RS;
-  float2* X = d.T + (size_t)(active ? row : 0) * H;
-  const size_t rbase = (size_t)(active ? row : 0) * N;
+  const uint32_t rowc = active ? row : 0;  // idle lanes: row 0, nothing stored
+  float2* const Tb = d.T;
+  const uint32_t xo = rowc * (uint32_t)H;      // row start in T (elements)
+  const uint32_t ro = rowc * (uint32_t)(N / 2);  // row start in a real field (voxel pairs)
+  const size_t rbase = (size_t)rowc * N;
   float2 v[E];
   double dat = 0.0;
+  // alpha, beta of the row (voxel pairs), loaded up front with the row of T;
+  // idle lanes read row 0 and store nothing
+  const bool data = MODE == Z_GRAD || (MODE == Z_C2R && (a.flags & ZF_DATA));
+  constexpr bool pre = HMC_ZPRE && (MODE == Z_GRAD || MODE == Z_C2R);
+  float2 al[pre ? E : 1], be[pre ? E : 1];
+  if constexpr (pre) {
+    if (data) {
+      const float2* ap = reinterpret_cast<const float2*>(d.alpha);
+      const float2* bp = reinterpret_cast<const float2*>(d.beta);
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        al[e] = ld_si(ap, ro + t + T * e);
+        be[e] = ld_si(bp, ro + t + T * e);
+      }
+    }
+  }
 
   if constexpr (MODE == Z_GRAD || MODE == Z_C2R) {
-    for (int k = t; k <= M; k += T) L[k] = active ? X[k] : make_float2(0.f, 0.f);
+    float2 xr[E + 1];
+#pragma unroll
+    for (int e = 0; e < E; ++e) xr[e] = gldi(Tb, xo + t + T * e);
+    xr[E] = gldi(Tb, xo + M);
+#pragma unroll
+    for (int e = 0; e < E; ++e) L[t + T * e] = xr[e];
+    if (t == 0) L[M] = xr[E];
     __syncthreads();
     // Z_k = (X_k + conj X_{M-k}) + i W_N^-k (X_k - conj X_{M-k}); imaginary parts of
     // the self-conjugate X_0 and X_M are dropped.
@@ -454,8 +611,7 @@ __device__ __forceinline__ void zpass(const ChainDev& d, int lt, const ZArgs a, 
   } else if constexpr (MODE == Z_R2C) {
 #pragma unroll
     for (int e = 0; e < E; ++e)
-      v[e] = active ? reinterpret_cast<const float2*>(a.src + rbase)[t + T * e]
-                    : make_float2(0.f, 0.f);
+      v[e] = gldi(reinterpret_cast<const float2*>(a.src), ro + t + T * e);
   } else {  // Z_NOISE: white noise w_i from Philox stream 3 (10: warm start), element = voxel index
     const uint32_t stream = (a.flags & ZF_WARM) ? hmcrng::kWarm : hmcrng::kMomenta;
 #pragma unroll
@@ -478,15 +634,19 @@ __device__ __forceinline__ void zpass(const ChainDev& d, int lt, const ZArgs a, 
     for (int e = 0; e < E; ++e) {
       const int n = t + T * e;
       const float2 x = v[e];
-      if (active && drout) reinterpret_cast<float2*>(drout + rbase)[n] = x;
-      if (MODE == Z_GRAD || (a.flags & ZF_DATA)) {
-        const float2 al = active ? ld_s(reinterpret_cast<const float2*>(d.alpha + rbase) + n)
-                                 : make_float2(0.f, 0.f);
-        const float2 be = active ? ld_s(reinterpret_cast<const float2*>(d.beta + rbase) + n)
-                                 : make_float2(0.f, 0.f);
+      if (active && drout) gsti(reinterpret_cast<float2*>(drout), ro + n, x);
+      if (data) {
+        float2 ae, bq;
+        if constexpr (pre) {
+          ae = al[e];
+          bq = be[e];
+        } else {
+          ae = ld_si(reinterpret_cast<const float2*>(d.alpha), ro + n);
+          bq = ld_si(reinterpret_cast<const float2*>(d.beta), ro + n);
+        }
         if (active && (a.flags & ZF_DATA))
-          dat += (0.5 * al.x * x.x - be.x) * (double)x.x + (0.5 * al.y * x.y - be.y) * (double)x.y;
-        v[e] = make_float2(al.x * x.x - be.x, al.y * x.y - be.y);
+          dat += (0.5 * ae.x * x.x - bq.x) * (double)x.x + (0.5 * ae.y * x.y - bq.y) * (double)x.y;
+        v[e] = make_float2(ae.x * x.x - bq.x, ae.y * x.y - bq.y);
       }
     }
   }
@@ -508,9 +668,9 @@ __device__ __forceinline__ void zpass(const ChainDev& d, int lt, const ZArgs a, 
         const float2 ev = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y + zc.y));
         const float2 df = csub(zk, zc);
         const float2 od = make_float2(0.5f * df.y, -0.5f * df.x);
-        X[k] = cadd(ev, cmul(twN[k], od));
+        gsti(Tb, xo + k, cadd(ev, cmul(twN[k], od)));
       }
-      if (t == 0) X[M] = make_float2(L[0].x - L[0].y, 0.f);
+      if (t == 0) gsti(Tb, xo + M, make_float2(L[0].x - L[0].y, 0.f));
     }
   }
   if (a.flags & ZF_DATA) {
@@ -526,7 +686,8 @@ __global__ void __launch_bounds__(kThreads) k_zpass(const ChainDev* __restrict__
                                                      const float2* __restrict__ tw) {
   extern __shared__ float2 lds[];
   __shared__ double red[4];
-  for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
+  for (TileWalk w = tile_walk(total); w.cur < w.end; w.cur += w.step) {
+    const int tile = w.cur;
     const int c = find_chain(ch, nch, tile, kTileZ);
     const ChainDev& d = ch[c];
     const int lt = tile - d.tb[kTileZ];
@@ -545,8 +706,8 @@ __global__ void __launch_bounds__(kThreads) k_zpass_n(const ChainDev* __restrict
                                                        const float2* __restrict__ tw) {
   extern __shared__ float2 lds[];
   __shared__ double red[4];
-  for (int b = blockIdx.x; b < total; b += gridDim.x) {
-    const int tile = gridDim.x == total ? tile_of(b, total) : b;
+  for (TileWalk w = tile_walk(total); w.cur < w.end; w.cur += w.step) {
+    const int tile = w.cur;
     const int c = find_chain(ch, nch, tile, kTileZ);
     const ChainDev& d = ch[c];
     zpass<N, MODE>(d, tile - d.tb[kTileZ], a, tw, lds, red);
@@ -708,7 +869,7 @@ __device__ __forceinline__ void xpass_l(const ChainDev& d, int lt, const XArgs a
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int kx = t + T * e;
-    const int m = shell_of(sfreq(kx, N), fy, kz, N, d.nb);
+    const int m = shell_of(d, sfreq(kx, N), fy, kz);
     const size_t idx = (size_t)kx * stride + col;
     const float il = m >= 0 ? d.tf[kTInvLam + m] : 0.f;
     if constexpr (MODE == L_START) {
@@ -789,7 +950,8 @@ __global__ void __launch_bounds__(kThreads) k_xpass_l(const ChainDev* __restrict
                                                        const float2* __restrict__ tw) {
   extern __shared__ float2 lds[];
   __shared__ double red[4];
-  for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
+  for (TileWalk w = tile_walk(total); w.cur < w.end; w.cur += w.step) {
+    const int tile = w.cur;
     const ChainDev& d = ch[find_chain(ch, nch, tile, kTileXY)];
     const int lt = tile - d.tb[kTileXY];
     switch (d.n) {
@@ -807,7 +969,8 @@ __global__ void __launch_bounds__(kThreads) k_zpass_l(const ChainDev* __restrict
                                                        const float2* __restrict__ tw) {
   extern __shared__ float2 lds[];
   __shared__ double red[4];
-  for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
+  for (TileWalk w = tile_walk(total); w.cur < w.end; w.cur += w.step) {
+    const int tile = w.cur;
     const ChainDev& d = ch[find_chain(ch, nch, tile, kTileZ)];
     const int lt = tile - d.tb[kTileZ];
     switch (d.n) {
@@ -841,6 +1004,13 @@ __global__ void __launch_bounds__(kThreads) k_mass_prep(const ChainDev* __restri
       __syncthreads();
     }
   }
+}
+
+__global__ void __launch_bounds__(kThreads) k_shell_lut(const ChainDev* __restrict__ ch) {
+  const ChainDev& d = ch[0];
+  const int qmax = 3 * (d.n / 2) * (d.n / 2);
+  for (int q = blockIdx.x * kThreads + threadIdx.x; q <= qmax; q += gridDim.x * kThreads)
+    d.lut[q] = (signed char)shell_q((uint64_t)q, d.n, d.nb);
 }
 
 // warm start: drn <- mu + sqrt(v / sigma^2) drn with v = exp(logvar), drn the
@@ -1108,7 +1278,7 @@ __global__ void __launch_bounds__(kThreads) k_energy_k(const ChainDev* __restric
       if (i >= d.nh) break;
       int fx, fy, kz;
       kindex(i, d.n, &fx, &fy, &kz);
-      const int m = shell_of(fx, fy, kz, d.n, d.nb);
+      const int m = shell_of(d, fx, fy, kz);
       if (m < 0) continue;
       const double w = (kz == 0 || kz == d.n / 2) ? 1.0 : 2.0;
       const float2 p = d.pk[i], x = d.dk[i];
@@ -1144,7 +1314,7 @@ __global__ void __launch_bounds__(kThreads) k_shell_power(const ChainDev* __rest
       if (i >= d.nh) break;
       int fx, fy, kz;
       kindex(i, d.n, &fx, &fy, &kz);
-      const int m = shell_of(fx, fy, kz, d.n, d.nb);
+      const int m = shell_of(d, fx, fy, kz);
       if (m < 0) continue;
       const double w = (kz == 0 || kz == d.n / 2) ? 1.0 : 2.0;
       const float2 x = d.dk[i];
@@ -1169,7 +1339,7 @@ __global__ void __launch_bounds__(kThreads) k_shell_index(const ChainDev* __rest
        i += (long long)gridDim.x * kThreads) {
     int fx, fy, kz;
     kindex(i, d.n, &fx, &fy, &kz);
-    out[i] = (int16_t)shell_of(fx, fy, kz, d.n, d.nb);
+    out[i] = (int16_t)shell_of(d, fx, fy, kz);
   }
 }
 
@@ -1194,7 +1364,7 @@ __global__ void __launch_bounds__(kThreads) k_commit_k(const ChainDev* __restric
       } else {
         int fx, fy, kz;
         kindex(i, d.n, &fx, &fy, &kz);
-        const int m = shell_of(fx, fy, kz, d.n, d.nb);
+        const int m = shell_of(d, fx, fy, kz);
         const float s = m >= 0 ? d.tf[kTScale + m] : 0.f;
         d.dk[i] = cscale(d.dk[i], s);
         d.gk[i] = d.bgk[i];
@@ -1463,6 +1633,10 @@ void launch_mass_prep(int phase, const ChainDev* ch, int total_r, const float* l
                       hipStream_t s) {
   hipLaunchKernelGGL(k_mass_prep, dim3(eg(total_r)), dim3(kThreads), 0, s, ch, total_r, logvar,
                      phase);
+}
+void launch_shell_lut(const ChainDev* ch, int n, hipStream_t s) {
+  const int q = 3 * (n / 2) * (n / 2) + 1;
+  hipLaunchKernelGGL(k_shell_lut, dim3((q + kThreads - 1) / kThreads), dim3(kThreads), 0, s, ch);
 }
 void launch_warm_combine(const ChainDev* ch, int total_r, const float* mu, const float* logvar,
                          hipStream_t s) {

@@ -33,7 +33,7 @@ struct Chain {
 };
 
 struct WsLayout {
-  size_t T, bdk, bgk, drn, part, shpart, mpart, T2, T3, shat, smass, total;
+  size_t T, bdk, bgk, drn, part, shpart, mpart, T2, T3, shat, smass, lut, total;
   int maxtiles;
 };
 
@@ -70,6 +70,7 @@ WsLayout layout(const hmc_config& c) {
   L.T3 = off; off = align256(off + nh * 8);
   L.shat = off; off = align256(off + nh * 8);
   L.smass = off; off = align256(off + nv * 4);
+  L.lut = off; off = align256(off + 3 * (size_t)(c.n / 2) * (c.n / 2) + 1);
   L.total = off;
   return L;
 }
@@ -96,7 +97,7 @@ struct hmc_ctx {
   double* pinned = nullptr;  // staging for host results
   int total[kTileClasses] = {0, 0, 0, 0};
   int lds_x = 0, lds_z = 0;
-  int grid_cap = 0;
+  int grid[3] = {0, 0, 0};  // launch grid per pass class (x, y, z); 0: one workgroup per tile
   int nsteps = 0;
   int uniform_n = 0;  // N shared by every chain (0 if sizes differ)
   int max_nb = 0, max_sub = 0;
@@ -181,30 +182,30 @@ struct Seq {
   void x(int mode, float kick, float drift, int flags) {
     Timed tm(c, mode == X_STEP ? 0 : 3, s);
     launch_xpass(mode, d, nch, tot[kTileXY], c->lds_x, XArgs{kick, drift, flags}, c->tw,
-                 c->grid_cap, s, un);
+                 c->grid[0], s, un);
     tm.done(s);
   }
   void y(int dir, int buf = 0) {
     Timed tm(c, 1, s);
-    launch_ypass(dir, d, nch, tot[kTileXY], c->lds_x, c->tw, c->grid_cap, s, un, buf);
+    launch_ypass(dir, d, nch, tot[kTileXY], c->lds_x, c->tw, c->grid[1], s, un, buf);
     tm.done(s);
   }
   void xl(int mode, float kick, float drift) {
     Timed tm(c, 3, s);
     launch_xpass_learned(mode, d, nch, tot[kTileXY], c->lds_x, XArgs{kick, drift, 0}, c->tw,
-                         c->grid_cap, s, un);
+                         c->grid[0], s, un);
     tm.done(s);
   }
   void zl(int mode, int flags) {
     Timed tm(c, 3, s);
     launch_zpass_learned(mode, d, nch, tot[kTileZ], c->lds_z, ZArgs{flags, 0, nullptr}, c->tw,
-                         c->grid_cap, s, un);
+                         c->grid[2], s, un);
     tm.done(s);
   }
   void z(int mode, int flags, const float* src = nullptr) {
     Timed tm(c, mode == Z_GRAD ? 2 : 3, s);
     launch_zpass(mode, d, nch, tot[kTileZ], c->lds_z, ZArgs{flags, 0, src}, c->tw,
-                 c->grid_cap, s, un);
+                 c->grid[2], s, un);
     tm.done(s);
   }
   // g_hat, delta and the data energy of the current delta_hat
@@ -452,6 +453,7 @@ hmc_status hmc_init_batch(const hmc_config* cfg, const hmc_buffers* buf, int32_t
     d.T3 = (float2*)(w + L.T3);
     d.shat = (float2*)(w + L.shat);
     d.smass = (float*)(w + L.smass);
+    d.lut = (signed char*)(w + L.lut);
     if (hipMalloc(&d.P, kPSize * sizeof(double)) != hipSuccess ||
         hipMalloc(&d.tf, kTSize * sizeof(float)) != hipSuccess ||
         hipMalloc(&d.td, kDSize * sizeof(double)) != hipSuccess ||
@@ -496,6 +498,7 @@ hmc_status hmc_init_batch(const hmc_config* cfg, const hmc_buffers* buf, int32_t
     if ((st = push_params(c, k)) != HMC_OK) return bail(st);
   if ((st = upload_desc(c)) != HMC_OK) return bail(st);
   const int nch = n_chains;
+  for (auto& k : c->ch) launch_shell_lut(k.solo, k.cfg.n, c->stream);
   // static data sums, mode counts, coefficients, tables, gradient of the initial state
   launch_static_moments(c->d_all, nch, c->total[kTileR], c->stream);
   launch_colsum(c->d_all, nch, 3 * c->max_sub, 1, kTileR, kS0, 1, c->stream);
@@ -843,6 +846,79 @@ hmc_status hmc_use_graph(hmc_ctx* c, int32_t enable) {
   if (!c) return fail(nullptr, HMC_EINVAL, "null context");
   c->use_graph = enable != 0;
   return HMC_OK;
+}
+
+static void drop_graphs(hmc_ctx* c) {
+  if (c->g_traj) (void)hipGraphExecDestroy(c->g_traj);
+  if (c->g_sweep) (void)hipGraphExecDestroy(c->g_sweep);
+  c->g_traj = c->g_sweep = nullptr;
+}
+
+static int class_tiles(hmc_ctx* c, int cls) { return c->total[cls == 2 ? kTileZ : kTileXY]; }
+
+hmc_status hmc_set_launch(hmc_ctx* c, int32_t cls, int32_t grid) {
+  if (!c || cls < 0 || cls > 2 || grid < 0) return fail(c, HMC_EINVAL, "bad argument");
+  c->grid[cls] = grid >= class_tiles(c, cls) ? 0 : grid;
+  drop_graphs(c);
+  return HMC_OK;
+}
+
+// One launch of the pass class on every chain.  The k-space pass runs with zero
+// kick and drift (it rewrites delta_hat and p_hat with their own values); the y
+// and real-space passes only touch the intermediate grid, which no call expects
+// to survive between calls.
+static void tune_launch(hmc_ctx* c, int cls) {
+  Seq q = seq_all(c);
+  if (cls == 0)
+    q.x(X_STEP, 0.f, 0.f, 0);
+  else if (cls == 1)
+    q.y(-1);
+  else
+    q.z(Z_GRAD, 0);
+}
+
+hmc_status hmc_autotune(hmc_ctx* c, int32_t reps, int32_t* chosen) {
+  if (!c || reps < 1) return fail(c, HMC_EINVAL, "bad argument");
+  int dev = 0, cus = 0;
+  HIPCHK(c, hipGetDevice(&dev));
+  HIPCHK(c, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const bool timing = c->timing;
+  c->timing = false;
+  hipEvent_t a = nullptr, b = nullptr;
+  HIPCHK(c, hipEventCreate(&a));
+  HIPCHK(c, hipEventCreate(&b));
+  const int mult[] = {0, 2, 3, 4, 5, 6, 8, 12};
+  hmc_status st = HMC_OK;
+  for (int cls = 0; cls < 3 && st == HMC_OK; ++cls) {
+    float best = 0.f;
+    int best_grid = 0;
+    for (int m : mult) {
+      const int grid = m * cus;
+      if (m > 0 && (grid >= class_tiles(c, cls) || grid % 8 != 0)) continue;
+      c->grid[cls] = grid;
+      tune_launch(c, cls);  // warm-up
+      if (hipEventRecord(a, c->stream) != hipSuccess) { st = HMC_EDEVICE; break; }
+      for (int r = 0; r < reps; ++r) tune_launch(c, cls);
+      if (hipEventRecord(b, c->stream) != hipSuccess || hipEventSynchronize(b) != hipSuccess) {
+        st = HMC_EDEVICE;
+        break;
+      }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, a, b);
+      if (best == 0.f || ms < best) {
+        best = ms;
+        best_grid = grid;
+      }
+    }
+    c->grid[cls] = best_grid;
+    if (chosen) chosen[cls] = best_grid;
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  c->timing = timing;
+  drop_graphs(c);
+  if (st != HMC_OK) return fail(c, st, "autotune: event failure");
+  return check_launch(c);
 }
 
 hmc_status hmc_timing(hmc_ctx* c, int32_t enable, double* ms, int64_t* launches) {
