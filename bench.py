@@ -14,6 +14,13 @@ The JSON line also carries:
   cpu_baseline  the float64 CPU oracle timed on this host on a bounded sample
                 of the same workload (a few leapfrog steps).
 
+--workload cfg4 times the batched pattern instead: 16 independent chains (8 at
+64^3, 6 at 128^3, 2 at 192^3, each with its own mask seed and 2-4 subsamples) in
+one launch per stage, sweeps replayed from a captured HIP graph, launch shapes
+from the autotuner; `value` is chain leapfrog steps per second and the line
+also gives the 256^3-equivalent rate (voxel updates / 256^3) and split R-hat of
+ln P(k) across same-size chains over the timed sweeps.
+
 --learned runs the learned warm start / mass comparison instead: the network
 is trained on plain-sampler draws from 64 seeded 128^3 mocks (four subsamples,
 40 shells), applied to the 256^3 survey, and the line reports P(k) ESS/s with
@@ -87,6 +94,77 @@ def cpu_baseline(mk, spec, budget_s):
                        f"{spec['n']}^3 workload, scipy.fft workers={workers}, {dt:.1f} s")
 
 
+BATCH_GROUPS = [("grp64", 8), ("grp128", 6), ("grp192", 2)]
+
+
+def batched_main(args):
+    import dataclasses
+
+    import torch
+    from paper_1306_1821_amd import diagnostics
+    from paper_1306_1821_amd.binding import Sampler
+    from synth import CONFIGS, make_mock
+
+    specs, owner, vox = [], [], 0
+    for name, count in BATCH_GROUPS:
+        for j in range(count):
+            cfg = dataclasses.replace(CONFIGS[name], seed=100 + len(specs), mask_seed=len(specs))
+            mk = make_mock(cfg, dtype=np.float32)
+            specs.append(dict(n=cfg.n, box=cfg.box, nb=cfg.nb, R=mk["R"], counts=mk["counts"],
+                              bias=mk["bias"], nbar=mk["nbar"], pk=mk["pk_init"],
+                              fixed_mask=cfg.fixed_mask, nsteps=cfg.nsteps, eps=args.eps_batch,
+                              rj=True, seed=2013, chain_id=len(specs), delta0=mk["delta"]))
+            owner.append(name)
+            vox += cfg.n ** 3
+    print(f"[bench] cfg4: {len(specs)} chains, {vox / 1e6:.1f} M voxels", file=sys.stderr,
+          flush=True)
+    s = Sampler(specs)
+    for i, sp in enumerate(specs):
+        s.set_state(i, sp["delta0"])
+    sweep = 0
+    for _ in range(args.warmup):
+        s.sweep(sweep)
+        sweep += 1
+    chosen = s.autotune(10)
+    s.use_graph(True)
+    s.sweep(sweep)                       # capture
+    sweep += 1
+    torch.cuda.synchronize()
+    acc, traces = [], [[] for _ in specs]
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = s.sweep(sweep)
+        sweep += 1
+        acc.append([o["accepted"] for o in out])
+        for i, o in enumerate(out):
+            traces[i].append(np.log(o["pk"]))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    nsteps = specs[0]["nsteps"]
+    rhat = {}
+    for name, count in BATCH_GROUPS:
+        t = np.array([traces[i] for i, o in enumerate(owner) if o == name])
+        rhat[name] = float(max(diagnostics.split_rhat(t[:, :, m]) for m in range(t.shape[2])))
+    s.close()
+    value = len(specs) * args.steps * nsteps / dt
+    out = {
+        "metric": "leapfrog steps/s, batched chains (16 chains: 8x64^3, 6x128^3, 2x192^3)",
+        "value": value, "unit": "chain leapfrog steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "cfg4: 16 independent chains in one launch per stage, "
+                               "8 at 64^3 (2 subsamples), 6 at 128^3 (4), 2 at 192^3 (3), one "
+                               "mask seed per chain, 30 leapfrog steps, joint move on; one "
+                               "step = one sweep of every chain", "eps": args.eps_batch},
+        "voxels": vox,
+        "equivalent_256_steps_per_s": value / len(specs) * vox / 256 ** 3,
+        "launch_grids": chosen,
+        "acceptance": float(np.mean(acc)),
+        "split_rhat_lnP_max": rhat,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def learned_main(args):
     import torch
     from paper_1306_1821_amd import learned
@@ -158,6 +236,7 @@ def main():
     ap.add_argument("--eps", type=float, default=0.02)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--eps-batch", type=float, default=0.03)
     ap.add_argument("--learned", action="store_true",
                     help="learned warm start / mass comparison (steps = measured sweeps per mass)")
     ap.add_argument("--mocks", type=int, default=64)
@@ -176,6 +255,8 @@ def main():
         if args.steps == 20:
             args.steps = 600
         return learned_main(args)
+    if args.workload == "cfg4":
+        return batched_main(args)
     import torch
     from paper_1306_1821_amd.binding import Sampler
 

@@ -81,3 +81,36 @@ def test_batched_chains_converge_together():
         print(name, "max split R-hat over shells", max(rh), "min bulk ESS",
               min(dg.ess_bulk(t[:, :, m]) for m in head))
         assert max(rh) < 1.1, (name, rh)
+
+
+@pytest.mark.parametrize("names", [("cfg1",), ("small16", "cfg1", "tiny8x2")])
+def test_launch_shapes_do_not_change_results(names):
+    """Persistent grids (XCD-aware tile walk) and the autotuner's choice give
+    bit-identical sweeps; the autotuner leaves the state unchanged."""
+    mks = [mock(n) for n in names]
+    specs = [chain_spec(m, eps=0.05, nsteps=8, seed=41, chain_id=i, rj=True)
+             for i, m in enumerate(mks)]
+    finals = []
+    for shape in ("default", 16, 20, 40, "auto"):
+        s = Sampler(specs)
+        for i, m in enumerate(mks):
+            s.set_state(i, start_state(m)[0])
+        if shape == "auto":
+            before = [s.state(i)["delta_k"] for i in range(len(mks))]
+            chosen = s.autotune(3)
+            assert len(chosen) == 3 and all(g >= 0 for g in chosen)
+            for i in range(len(mks)):
+                assert np.array_equal(s.state(i)["delta_k"], before[i])
+        elif shape != "default":
+            for cls in range(3):
+                s.set_launch(cls, shape)
+        stats = [s.sweep(sw) for sw in range(3)]
+        finals.append(([s.state(i)["delta_k"] for i in range(len(mks))],
+                       [[x["pk"] for x in st] for st in stats]))
+        s.close()
+    for dk, pk in finals[1:]:
+        for a, b in zip(dk, finals[0][0]):
+            assert np.array_equal(a, b)
+        for sw_a, sw_b in zip(pk, finals[0][1]):
+            for a, b in zip(sw_a, sw_b):
+                assert np.array_equal(a, b)
