@@ -733,7 +733,13 @@ __device__ __forceinline__ void row_c2r(const float2* X, float2* L, float2* v, i
                                         const float2* __restrict__ twM) {
   using C = ZC<N>;
   constexpr int M = N / 2, T = C::T, E = M / T;
-  for (int k = t; k <= M; k += T) L[k] = active ? X[k] : make_float2(0.f, 0.f);
+  float2 xr[E + 1];
+#pragma unroll
+  for (int e = 0; e < E; ++e) xr[e] = gld(X + t + T * e);  // X: an in-bounds row for idle lanes
+  xr[E] = gld(X + M);
+#pragma unroll
+  for (int e = 0; e < E; ++e) L[t + T * e] = xr[e];
+  if (t == 0) L[M] = xr[E];
   __syncthreads();
 #pragma unroll
   for (int e = 0; e < E; ++e) {
@@ -773,9 +779,9 @@ __device__ __forceinline__ void row_r2c(float2* v, float2* L, float2* X, int t, 
       const float2 ev = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y + zc.y));
       const float2 df = csub(zk, zc);
       const float2 od = make_float2(0.5f * df.y, -0.5f * df.x);
-      X[k] = cadd(ev, cmul(twN[k], od));
+      gst(X + k, cadd(ev, cmul(twN[k], od)));
     }
-    if (t == 0) X[M] = make_float2(L[0].x - L[0].y, 0.f);
+    if (t == 0) gst(X + M, make_float2(L[0].x - L[0].y, 0.f));
   }
   __syncthreads();
 }
@@ -792,13 +798,21 @@ __device__ __forceinline__ void zpass_l(const ChainDev& d, int lt, const ZArgs a
   const int row = lt * B + b;
   const bool active = row < N * N;
   float2* L = lds + b * RS;
-  const size_t roff = (size_t)(active ? row : 0) * H;
-  const size_t rbase = (size_t)(active ? row : 0) * N;
-  const float2* sm = reinterpret_cast<const float2*>(d.smass + rbase);
-  float2 v[E];
+  const uint32_t rowc = active ? row : 0;  // idle lanes: row 0, nothing stored
+  const uint32_t roff = rowc * (uint32_t)H;
+  const uint32_t ro = rowc * (uint32_t)(N / 2);
+  const float2* sm = reinterpret_cast<const float2*>(d.smass);
+  float2 v[E], s[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) s[e] = gldi(sm, ro + t + T * e);
   double sum = 0.0, dat = 0.0;
   if constexpr (MODE == LZ_FORCE) {
-    float2 w[E];
+    float2 al[E], be[E], w[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      al[e] = ld_si(reinterpret_cast<const float2*>(d.alpha), ro + t + T * e);
+      be[e] = ld_si(reinterpret_cast<const float2*>(d.beta), ro + t + T * e);
+    }
     row_c2r<N>(d.T3 + roff, L, w, t, active, twN, twM);  // prior force F^-1(delta_hat/lambda)
     row_c2r<N>(d.T + roff, L, v, t, active, twN, twM);   // delta
     float* drout = (a.flags & ZF_WRITE_DRN) ? d.drn : (a.flags & ZF_WRITE_DR) ? d.dr : nullptr;
@@ -806,26 +820,20 @@ __device__ __forceinline__ void zpass_l(const ChainDev& d, int lt, const ZArgs a
     for (int e = 0; e < E; ++e) {
       const int n = t + T * e;
       const float2 x = v[e], fp = w[e];
-      const float2 z2 = make_float2(0.f, 0.f);
-      const float2 al = active ? ld_s(reinterpret_cast<const float2*>(d.alpha + rbase) + n) : z2;
-      const float2 be = active ? ld_s(reinterpret_cast<const float2*>(d.beta + rbase) + n) : z2;
-      const float2 s = active ? sm[n] : z2;
-      if (active && drout) reinterpret_cast<float2*>(drout + rbase)[n] = x;
-      const float g0 = fp.x + al.x * x.x - be.x, g1 = fp.y + al.y * x.y - be.y;
+      if (active && drout) gsti(reinterpret_cast<float2*>(drout), ro + n, x);
+      const float g0 = fp.x + al[e].x * x.x - be[e].x, g1 = fp.y + al[e].y * x.y - be[e].y;
       if (active) {
         sum += (double)g0 + (double)g1;
         if (a.flags & ZF_DATA)
-          dat += (0.5 * al.x * x.x - be.x) * (double)x.x + (0.5 * al.y * x.y - be.y) * (double)x.y;
+          dat += (0.5 * al[e].x * x.x - be[e].x) * (double)x.x +
+                 (0.5 * al[e].y * x.y - be[e].y) * (double)x.y;
       }
-      v[e] = make_float2(s.x * g0, s.y * g1);
+      v[e] = make_float2(s[e].x * g0, s[e].y * g1);
     }
   } else {
     row_c2r<N>(d.T2 + roff, L, v, t, active, twN, twM);
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const float2 s = active ? sm[t + T * e] : make_float2(0.f, 0.f);
-      v[e] = make_float2(s.x * v[e].x, s.y * v[e].y);
-    }
+    for (int e = 0; e < E; ++e) v[e] = make_float2(s[e].x * v[e].x, s[e].y * v[e].y);
   }
   row_r2c<N>(v, L, (MODE == LZ_FORCE ? d.T : d.T2) + roff, t, active, twN, twM);
   if constexpr (MODE == LZ_FORCE) {
@@ -845,73 +853,83 @@ __device__ __forceinline__ void xpass_l(const ChainDev& d, int lt, const XArgs a
                                         double* red) {
   using C = XC<N>;
   constexpr int T = C::T, B = C::B, E = N / T, H = N / 2 + 1, ES = B + 1;
+  constexpr uint32_t stride = (uint32_t)N * H;
   const float2* tw = twall + tw_offset(N);
   const int tid = threadIdx.x, b = tid % B, t = tid / B;
   const int col = lt * B + b;
   const bool active = col < N * H;
-  const size_t stride = (size_t)N * H;
-  const int ky = active ? col / H : 0, kz = active ? col % H : 0;
+  const uint32_t colc = active ? col : 0;  // idle lanes: column 0, nothing stored
+  const int ky = colc / H, kz = colc % H;
   const int fy = sfreq(ky, N);
+  const int q0 = fy * fy + kz * kz;
   const double wz = (kz == 0 || kz == N / 2) ? 1.0 : 2.0;
   const float norm = d.norm;
   const float kick = a.kick * d.eps, drift = a.drift * d.eps;
   constexpr bool KICK = MODE == L_KICK || MODE == L_KICK_LAST;
+  const float* const tf = d.tf;
+  const double* const td = d.td;
   float2* L = lds + b;
   const float2* src = MODE == L_DRIFT ? d.T2 : d.T;
-  float2 v[E], w[E];
+  auto offs = [&](int e) { return colc + (uint32_t)(t + T * e) * stride; };
+  float2 v[E], w[E], sv[E];
+  int m[E];
 #pragma unroll
-  for (int e = 0; e < E; ++e)
-    v[e] = active ? src[(size_t)(t + T * e) * stride + col] : make_float2(0.f, 0.f);
+  for (int e = 0; e < E; ++e) {
+    const int fx = sfreq(t + T * e, N);
+    m[e] = shell_lut(d.lut, q0 + fx * fx);
+    v[e] = gldi(src, offs(e));
+    sv[e] = MODE == L_START || MODE == L_DRIFT ? xld(d.dk, offs(e)) : xld(d.pk, offs(e));
+    w[e] = KICK ? gldi(d.shat, offs(e)) : MODE == L_START ? gldi(d.gk, offs(e))
+                                                          : make_float2(0.f, 0.f);
+  }
   fft<N, T, +1>(v, L, ES, t, active, tw, typename C::RL{});
   const float gbar = KICK ? (float)d.P[kGbar] : 0.f;
   double acc0 = 0.0, acc1 = 0.0;
   const float2 z2 = make_float2(0.f, 0.f);
 #pragma unroll
   for (int e = 0; e < E; ++e) {
-    const int kx = t + T * e;
-    const int m = shell_of(d, sfreq(kx, N), fy, kz);
-    const size_t idx = (size_t)kx * stride + col;
-    const float il = m >= 0 ? d.tf[kTInvLam + m] : 0.f;
+    const int me = m[e];
+    const float il = me >= 0 ? gldf(tf + kTInvLam + me) : 0.f;
     if constexpr (MODE == L_START) {
-      const float sq = m >= 0 ? d.tf[kTSqrtMass + m] : 0.f;
+      const float sq = me >= 0 ? gldf(tf + kTSqrtMass + me) : 0.f;
       const float2 pk = cscale(v[e], norm * sq);
-      const float2 dk = active && m >= 0 ? ld_s(d.dk + idx) : z2;
+      const float2 dk = me >= 0 ? sv[e] : z2;
       if (active) {
-        d.bdk[idx] = dk;
-        d.bgk[idx] = d.gk[idx];
-        st_s(d.pk + idx, pk);
-        if (m >= 0) {
-          acc0 += wz * ((double)pk.x * pk.x + (double)pk.y * pk.y) * d.td[kDInvMass + m];
-          acc1 += wz * ((double)dk.x * dk.x + (double)dk.y * dk.y) * d.td[kDInvLam + m];
+        gsti(d.bdk, offs(e), dk);
+        gsti(d.bgk, offs(e), w[e]);
+        xst(d.pk, offs(e), pk);
+        if (me >= 0) {
+          acc0 += wz * ((double)pk.x * pk.x + (double)pk.y * pk.y) * gldd(td + kDInvMass + me);
+          acc1 += wz * ((double)dk.x * dk.x + (double)dk.y * dk.y) * gldd(td + kDInvLam + me);
         }
       }
       v[e] = cscale(dk, norm);
       w[e] = cscale(dk, norm * il);
     } else if constexpr (MODE == L_DRIFT) {
-      float2 dk = active && m >= 0 ? ld_s(d.dk + idx) : z2;
-      if (m >= 0) {
+      float2 dk = me >= 0 ? sv[e] : z2;
+      if (me >= 0) {
         dk.x += drift * norm * v[e].x;
         dk.y += drift * norm * v[e].y;
       }
-      if (active) st_s(d.dk + idx, dk);
+      if (active) xst(d.dk, offs(e), dk);
       v[e] = cscale(dk, norm);
       w[e] = cscale(dk, norm * il);
     } else {
-      float2 pk = active && m >= 0 ? ld_s(d.pk + idx) : z2;
-      if (m >= 0) {
-        const float2 sh = active ? d.shat[idx] : z2;
+      float2 pk = me >= 0 ? sv[e] : z2;
+      if (me >= 0) {
+        const float2 sh = w[e];
         pk.x -= kick * (norm * v[e].x - gbar * sh.x);
         pk.y -= kick * (norm * v[e].y - gbar * sh.y);
       }
-      if (active) st_s(d.pk + idx, pk);
+      if (active) xst(d.pk, offs(e), pk);
       if constexpr (MODE == L_KICK_LAST) {
-        if (active && m >= 0) {
-          const float2 dk = ld_s(d.dk + idx);
-          acc0 += wz * ((double)pk.x * pk.x + (double)pk.y * pk.y) * d.td[kDInvMass + m];
-          acc1 += wz * ((double)dk.x * dk.x + (double)dk.y * dk.y) * d.td[kDInvLam + m];
+        if (active && me >= 0) {
+          const float2 dk = xld(d.dk, offs(e));
+          acc0 += wz * ((double)pk.x * pk.x + (double)pk.y * pk.y) * gldd(td + kDInvMass + me);
+          acc1 += wz * ((double)dk.x * dk.x + (double)dk.y * dk.y) * gldd(td + kDInvLam + me);
         }
       } else {
-        v[e] = m >= 0 ? cscale(pk, norm * d.tf[kTInvMass + m]) : z2;
+        v[e] = me >= 0 ? cscale(pk, norm * gldf(tf + kTInvMass + me)) : z2;
       }
     }
   }
@@ -919,18 +937,18 @@ __device__ __forceinline__ void xpass_l(const ChainDev& d, int lt, const XArgs a
     fft<N, T, -1>(v, L, ES, t, active, tw, typename C::RL{});
     if (active) {
 #pragma unroll
-      for (int e = 0; e < E; ++e) d.T[(size_t)(t + T * e) * stride + col] = v[e];
+      for (int e = 0; e < E; ++e) gsti(d.T, offs(e), v[e]);
     }
     fft<N, T, -1>(w, L, ES, t, active, tw, typename C::RL{});
     if (active) {
 #pragma unroll
-      for (int e = 0; e < E; ++e) d.T3[(size_t)(t + T * e) * stride + col] = w[e];
+      for (int e = 0; e < E; ++e) gsti(d.T3, offs(e), w[e]);
     }
   } else if constexpr (MODE == L_KICK) {
     fft<N, T, -1>(v, L, ES, t, active, tw, typename C::RL{});
     if (active) {
 #pragma unroll
-      for (int e = 0; e < E; ++e) d.T2[(size_t)(t + T * e) * stride + col] = v[e];
+      for (int e = 0; e < E; ++e) gsti(d.T2, offs(e), v[e]);
     }
   }
   if constexpr (MODE == L_START || MODE == L_KICK_LAST) {
@@ -979,6 +997,30 @@ __global__ void __launch_bounds__(kThreads) k_zpass_l(const ChainDev* __restrict
 #undef C
       default: break;
     }
+  }
+}
+
+// single-size variants of the learned passes (every chain of the launch has this N)
+template <int N, int MODE>
+__global__ void __launch_bounds__(kThreads) k_xpass_l_n(const ChainDev* __restrict__ ch, int nch,
+                                                         int total, XArgs a,
+                                                         const float2* __restrict__ tw) {
+  extern __shared__ float2 lds[];
+  __shared__ double red[4];
+  for (TileWalk w = tile_walk(total); w.cur < w.end; w.cur += w.step) {
+    const ChainDev& d = ch[find_chain(ch, nch, w.cur, kTileXY)];
+    xpass_l<N, MODE>(d, w.cur - d.tb[kTileXY], a, tw, lds, red);
+  }
+}
+template <int N, int MODE>
+__global__ void __launch_bounds__(kThreads) k_zpass_l_n(const ChainDev* __restrict__ ch, int nch,
+                                                         int total, ZArgs a,
+                                                         const float2* __restrict__ tw) {
+  extern __shared__ float2 lds[];
+  __shared__ double red[4];
+  for (TileWalk w = tile_walk(total); w.cur < w.end; w.cur += w.step) {
+    const ChainDev& d = ch[find_chain(ch, nch, w.cur, kTileZ)];
+    zpass_l<N, MODE>(d, w.cur - d.tb[kTileZ], a, tw, lds, red);
   }
 }
 
@@ -1609,9 +1651,27 @@ __global__ void __launch_bounds__(kThreads) k_rj(const ChainDev* __restrict__ ch
 // ------------------------------------------------------------------ launch wrappers
 static inline int eg(int total) { return total < 4096 ? total : 4096; }
 
+template <int N>
+static void launch_xl_n(int mode, dim3 g, dim3 bl, int lds, hipStream_t s, const ChainDev* ch,
+                        int nch, int total, XArgs a, const float2* tw) {
+  switch (mode) {
+    case L_START: hipLaunchKernelGGL((k_xpass_l_n<N, L_START>), g, bl, lds, s, ch, nch, total, a, tw); break;
+    case L_DRIFT: hipLaunchKernelGGL((k_xpass_l_n<N, L_DRIFT>), g, bl, lds, s, ch, nch, total, a, tw); break;
+    case L_KICK: hipLaunchKernelGGL((k_xpass_l_n<N, L_KICK>), g, bl, lds, s, ch, nch, total, a, tw); break;
+    case L_KICK_LAST:
+      hipLaunchKernelGGL((k_xpass_l_n<N, L_KICK_LAST>), g, bl, lds, s, ch, nch, total, a, tw);
+      break;
+  }
+}
 void launch_xpass_learned(int mode, const ChainDev* ch, int nch, int total, int lds, XArgs a,
-                          const float2* tw, int cap, hipStream_t s, int) {
+                          const float2* tw, int cap, hipStream_t s, int uniform_n) {
   dim3 g(grid_of(total, cap)), bl(kThreads);
+  switch (uniform_n) {
+#define C(NN) case NN: launch_xl_n<NN>(mode, g, bl, lds, s, ch, nch, total, a, tw); return;
+    HMC_FOR_N(C)
+#undef C
+    default: break;
+  }
   switch (mode) {
     case L_START: hipLaunchKernelGGL(k_xpass_l<L_START>, g, bl, lds, s, ch, nch, total, a, tw); break;
     case L_DRIFT: hipLaunchKernelGGL(k_xpass_l<L_DRIFT>, g, bl, lds, s, ch, nch, total, a, tw); break;
@@ -1622,8 +1682,20 @@ void launch_xpass_learned(int mode, const ChainDev* ch, int nch, int total, int 
   }
 }
 void launch_zpass_learned(int mode, const ChainDev* ch, int nch, int total, int lds, ZArgs a,
-                          const float2* tw, int cap, hipStream_t s, int) {
+                          const float2* tw, int cap, hipStream_t s, int uniform_n) {
   dim3 g(grid_of(total, cap)), bl(kThreads);
+  switch (uniform_n) {
+#define C(NN)                                                                               \
+  case NN:                                                                                  \
+    if (mode == LZ_FORCE)                                                                   \
+      hipLaunchKernelGGL((k_zpass_l_n<NN, LZ_FORCE>), g, bl, lds, s, ch, nch, total, a, tw); \
+    else                                                                                    \
+      hipLaunchKernelGGL((k_zpass_l_n<NN, LZ_VEL>), g, bl, lds, s, ch, nch, total, a, tw);   \
+    return;
+    HMC_FOR_N(C)
+#undef C
+    default: break;
+  }
   if (mode == LZ_FORCE)
     hipLaunchKernelGGL(k_zpass_l<LZ_FORCE>, g, bl, lds, s, ch, nch, total, a, tw);
   else
