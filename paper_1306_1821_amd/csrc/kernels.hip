@@ -23,6 +23,15 @@
 #endif
 // non-temporal hints on the state in the k-space pass (HMC_XNT) and on alpha,
 // beta in the real-space pass (HMC_NT)
+#ifndef HMC_LDS_TAB
+#define HMC_LDS_TAB 1
+#endif
+#ifndef HMC_SHELL_LUT
+#define HMC_SHELL_LUT 0
+#endif
+#ifndef HMC_ZPAD
+#define HMC_ZPAD 1
+#endif
 #ifndef HMC_ZPRE
 #define HMC_ZPRE 1
 #endif
@@ -172,7 +181,17 @@ template <> struct ZC<256> { static constexpr int T = 8, B = 32;  using RL = Rad
 #endif
 
 template <int N> constexpr int xlds() { return N * (XC<N>::B + 1) * 8; }
-template <int N> constexpr int zlds() { return ZC<N>::B * (N / 2 + 2) * 8; }
+// z-pass LDS row stride in float2: at least M + 2; for M >= 64 rounded up to
+// 16 mod 32 so that the two rows a half-wave reads fall on disjoint LDS banks
+template <int N> constexpr int zrs() {
+  constexpr int M = N / 2;
+  if constexpr (M < 64 || !HMC_ZPAD) {
+    return M + 2;
+  } else {
+    return ((M + 2 + 15) / 32) * 32 + 16;
+  }
+}
+template <int N> constexpr int zlds() { return ZC<N>::B * zrs<N>() * 8; }
 
 #define HMC_FOR_N(X) X(8) X(16) X(32) X(64) X(128) X(192) X(256)
 
@@ -264,6 +283,20 @@ __device__ __forceinline__ int shell_q(uint64_t q, int n, int nb) {
   while (t > 1 && (uint64_t)(t - 1) * (uint64_t)(t - 1) * qmax >= lhs) --t;
   return t - 1;
 }
+// The same rule evaluated in 32-bit integers with one float square root (exact for
+// N <= 256, nb <= 128: nb^2 q and (m+1)^2 q_max stay below 2^31); the square root
+// lands within one of the answer and one integer comparison each way corrects it.
+__device__ __forceinline__ int shell_fast(uint32_t q, uint32_t qmax, float inv_qmax, uint32_t nb) {
+  if (q == 0) return -1;
+  const uint32_t lhs = nb * nb * q;
+  int t = (int)ceilf(sqrtf((float)lhs * inv_qmax));
+  t = t < 1 ? 1 : t;
+  if ((uint32_t)(t * t) * qmax < lhs)
+    ++t;
+  else if (t > 1 && (uint32_t)((t - 1) * (t - 1)) * qmax >= lhs)
+    --t;
+  return t - 1;
+}
 __device__ __forceinline__ int shell_of(const ChainDev& d, int fx, int fy, int fz) {
   return shell_lut(d.lut, fx * fx + fy * fy + fz * fz);
 }
@@ -323,14 +356,32 @@ __device__ __forceinline__ void xpass(const ChainDev& d, int lt, const XArgs a, 
   float2* const pkb = d.pk;
   float2* const gkb = d.gk;
   const signed char* const lut = d.lut;
+#if HMC_LDS_TAB
+  // per-shell float tables of the chain in LDS (indexed gathers stay on chip)
+  __shared__ float stf[4 * kMaxBins];
+  for (int i = tid; i < 4 * kMaxBins; i += kThreads) stf[i] = (i % kMaxBins) < d.nb ? gldf(d.tf + i) : 0.f;
+  __syncthreads();
+  const float* const tf = stf;
+#else
   const float* const tf = d.tf;
+#endif
   const double* const td = d.td;
   float2* L = lds + b;
   float2 v[E];
   auto offs = [&](int e) { return colc + (uint32_t)(t + T * e) * stride; };
+  constexpr uint32_t qmax = 3u * (N / 2) * (N / 2);
+  const float inv_qmax = 1.f / (float)qmax;
+  const uint32_t nbu = (uint32_t)d.nb;
   auto shell = [&](int e) {
     const int fx = sfreq(t + T * e, N);
+#if HMC_SHELL_LUT
+    (void)inv_qmax;
+    (void)nbu;
     return shell_lut(lut, q0 + fx * fx);
+#else
+    (void)lut;
+    return shell_fast((uint32_t)(q0 + fx * fx), qmax, inv_qmax, nbu);
+#endif
   };
 
   const bool dot = (MODE == X_FWD) && (a.flags & XF_DOT);
@@ -349,7 +400,7 @@ __device__ __forceinline__ void xpass(const ChainDev& d, int lt, const XArgs a, 
       const int me = shell(e);
       const float2 x = gldi(dkb, offs(e));
       float s = norm;
-      if ((a.flags & XF_SCALE) && me >= 0) s *= gldf(tf + kTScale + me);
+      if ((a.flags & XF_SCALE) && me >= 0) s *= tf[kTScale + me];
       if ((a.flags & XF_PRIOR) && me >= 0) s *= (float)sqrt(gldd(d.P + kLam + me));
       v[e] = me < 0 ? make_float2(0.f, 0.f) : cscale(x, s);
     }
@@ -367,7 +418,7 @@ __device__ __forceinline__ void xpass(const ChainDev& d, int lt, const XArgs a, 
       }
       if (dot && active && me >= 0) {
         const float2 x = gldi(dkb, offs(e));
-        const float s = (a.flags & XF_SCALE) ? gldf(tf + kTScale + me) : 1.f;
+        const float s = (a.flags & XF_SCALE) ? tf[kTScale + me] : 1.f;
         const double val = wz * ((double)(s * x.x) * g.x + (double)(s * x.y) * g.y);
         atomicAdd(&bins[(threadIdx.x >> 6) * kMaxBins + me], val);
       }
@@ -386,12 +437,12 @@ __device__ __forceinline__ void xpass(const ChainDev& d, int lt, const XArgs a, 
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int me = m[e];
-      const float il = me >= 0 ? gldf(tf + kTInvLam + me) : 0.f;
-      const float im = me >= 0 ? gldf(tf + kTInvMass + me) : 0.f;
+      const float il = me >= 0 ? tf[kTInvLam + me] : 0.f;
+      const float im = me >= 0 ? tf[kTInvMass + me] : 0.f;
       float2 dk = dkv[e], pk, g;
       if constexpr (MODE == X_START) {
         // fresh momentum p_hat = sqrt(m_k) F w; gradient of the current state from memory
-        const float sq = me >= 0 ? gldf(tf + kTSqrtMass + me) : 0.f;
+        const float sq = me >= 0 ? tf[kTSqrtMass + me] : 0.f;
         pk = cscale(v[e], norm * sq);
         g = pkv[e];
         if (active) {
@@ -552,7 +603,7 @@ template <int N, int MODE>
 __device__ __forceinline__ void zpass(const ChainDev& d, int lt, const ZArgs a, const float2* __restrict__ twall,
                       float2* lds, double* red) {
   using C = ZC<N>;
-  constexpr int M = N / 2, T = C::T, B = C::B, E = M / T, H = M + 1, RS = M + 2;
+  constexpr int M = N / 2, T = C::T, B = C::B, E = M / T, H = M + 1, RS = zrs<N>();
   const float2* twM = twall + tw_offset(M);
   const float2* twN = twall + tw_offset(N);
   const int tid = threadIdx.x, t = tid % T, b = tid / T;
@@ -791,7 +842,7 @@ __device__ __forceinline__ void zpass_l(const ChainDev& d, int lt, const ZArgs a
                                         const float2* __restrict__ twall, float2* lds,
                                         double* red) {
   using C = ZC<N>;
-  constexpr int M = N / 2, T = C::T, B = C::B, E = M / T, H = M + 1, RS = M + 2;
+  constexpr int M = N / 2, T = C::T, B = C::B, E = M / T, H = M + 1, RS = zrs<N>();
   const float2* twM = twall + tw_offset(M);
   const float2* twN = twall + tw_offset(N);
   const int tid = threadIdx.x, t = tid % T, b = tid / T;
@@ -866,8 +917,13 @@ __device__ __forceinline__ void xpass_l(const ChainDev& d, int lt, const XArgs a
   const float norm = d.norm;
   const float kick = a.kick * d.eps, drift = a.drift * d.eps;
   constexpr bool KICK = MODE == L_KICK || MODE == L_KICK_LAST;
-  const float* const tf = d.tf;
+  __shared__ float stf[4 * kMaxBins];
+  for (int i = tid; i < 4 * kMaxBins; i += kThreads) stf[i] = (i % kMaxBins) < d.nb ? gldf(d.tf + i) : 0.f;
+  __syncthreads();
+  const float* const tf = stf;
   const double* const td = d.td;
+  constexpr uint32_t qmax = 3u * (N / 2) * (N / 2);
+  const float inv_qmax = 1.f / (float)qmax;
   float2* L = lds + b;
   const float2* src = MODE == L_DRIFT ? d.T2 : d.T;
   auto offs = [&](int e) { return colc + (uint32_t)(t + T * e) * stride; };
@@ -876,7 +932,7 @@ __device__ __forceinline__ void xpass_l(const ChainDev& d, int lt, const XArgs a
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int fx = sfreq(t + T * e, N);
-    m[e] = shell_lut(d.lut, q0 + fx * fx);
+    m[e] = shell_fast((uint32_t)(q0 + fx * fx), qmax, inv_qmax, (uint32_t)d.nb);
     v[e] = gldi(src, offs(e));
     sv[e] = MODE == L_START || MODE == L_DRIFT ? xld(d.dk, offs(e)) : xld(d.pk, offs(e));
     w[e] = KICK ? gldi(d.shat, offs(e)) : MODE == L_START ? gldi(d.gk, offs(e))
@@ -889,9 +945,9 @@ __device__ __forceinline__ void xpass_l(const ChainDev& d, int lt, const XArgs a
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int me = m[e];
-    const float il = me >= 0 ? gldf(tf + kTInvLam + me) : 0.f;
+    const float il = me >= 0 ? tf[kTInvLam + me] : 0.f;
     if constexpr (MODE == L_START) {
-      const float sq = me >= 0 ? gldf(tf + kTSqrtMass + me) : 0.f;
+      const float sq = me >= 0 ? tf[kTSqrtMass + me] : 0.f;
       const float2 pk = cscale(v[e], norm * sq);
       const float2 dk = me >= 0 ? sv[e] : z2;
       if (active) {
@@ -929,7 +985,7 @@ __device__ __forceinline__ void xpass_l(const ChainDev& d, int lt, const XArgs a
           acc1 += wz * ((double)dk.x * dk.x + (double)dk.y * dk.y) * gldd(td + kDInvLam + me);
         }
       } else {
-        v[e] = me >= 0 ? cscale(pk, norm * gldf(tf + kTInvMass + me)) : z2;
+        v[e] = me >= 0 ? cscale(pk, norm * tf[kTInvMass + me]) : z2;
       }
     }
   }
@@ -1163,28 +1219,50 @@ void launch_zpass(int mode, const ChainDev* ch, int nch, int total, int lds, ZAr
 // Real-space tiles cover kElemPerTile voxels; k-space tiles kElemPerTile modes.
 
 // alpha, beta from R, counts, bias, Nbar (voxels with R > 0 only); partial sum of alpha.
+// real fields are read 4 voxels at a time (N^3 and the tile size are multiples of 4)
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) f4v gf4v;
+__device__ __forceinline__ f4v gld4(const float* base, uint32_t i4) {
+  return *(const gf4v*)((const gchar*)base + i4 * 16u);
+}
+__device__ __forceinline__ void gst4(float* base, uint32_t i4, f4v v) {
+  *(gf4v*)((gchar*)base + i4 * 16u) = v;
+}
+
 __global__ void __launch_bounds__(kThreads) k_coeff(const ChainDev* __restrict__ ch, int nch,
                                                      int total) {
   __shared__ double red[4];
+  __shared__ float cb2n[kMaxSub], cb[kMaxSub], cn[kMaxSub];
   for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
     const ChainDev& d = ch[find_chain(ch, nch, tile, kTileR)];
     const int lt = tile - d.tb[kTileR];
+    if (threadIdx.x < d.nsub) {
+      const float bl = (float)d.P[kBias + threadIdx.x], nb = (float)d.P[kNbar + threadIdx.x];
+      cb2n[threadIdx.x] = bl * bl * nb;
+      cb[threadIdx.x] = bl;
+      cn[threadIdx.x] = nb;
+    }
+    __syncthreads();
+    const uint32_t nv4 = (uint32_t)(d.nv / 4), base4 = (uint32_t)lt * (kElemPerTile / 4);
     double acc = 0.0;
-    for (int j = threadIdx.x; j < kElemPerTile; j += kThreads) {
-      const long long i = (long long)lt * kElemPerTile + j;
-      if (i >= d.nv) break;
-      float al = 0.f, be = 0.f;
+    for (uint32_t j = threadIdx.x; j < kElemPerTile / 4; j += kThreads) {
+      const uint32_t i4 = base4 + j;
+      if (i4 >= nv4) break;
+      f4v al = {0.f, 0.f, 0.f, 0.f}, be = {0.f, 0.f, 0.f, 0.f};
       for (int l = 0; l < d.nsub; ++l) {
-        const float r = d.R[(size_t)l * d.nv + i];
-        if (r > 0.f) {
-          const float bl = (float)d.P[kBias + l], nb = (float)d.P[kNbar + l];
-          al += bl * bl * nb * r;
-          be += bl * (d.counts[(size_t)l * d.nv + i] - nb * r);
+        const f4v r = gld4(d.R + (size_t)l * d.nv, i4);
+        const f4v c = gld4(d.counts + (size_t)l * d.nv, i4);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (r[q] > 0.f) {
+            al[q] += cb2n[l] * r[q];
+            be[q] += cb[l] * (c[q] - cn[l] * r[q]);
+          }
         }
       }
-      d.alpha[i] = al;
-      d.beta[i] = be;
-      acc += al;
+      gst4(d.alpha, i4, al);
+      gst4(d.beta, i4, be);
+      acc += (double)al[0] + (double)al[1] + (double)al[2] + (double)al[3];
     }
     const double s = block_sum(acc, red);
     if (threadIdx.x == 0) d.part[kPartAlpha * d.maxtiles + lt] = s;
@@ -1252,17 +1330,23 @@ __global__ void __launch_bounds__(kThreads) k_moments(const ChainDev* __restrict
   for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
     const ChainDev& d = ch[find_chain(ch, nch, tile, kTileR)];
     const int lt = tile - d.tb[kTileR];
+    const uint32_t nv4 = (uint32_t)(d.nv / 4), base4 = (uint32_t)lt * (kElemPerTile / 4);
     for (int l = 0; l < d.nsub; ++l) {
       double s1 = 0.0, s2 = 0.0, st = 0.0;
-      for (int j = threadIdx.x; j < kElemPerTile; j += kThreads) {
-        const long long i = (long long)lt * kElemPerTile + j;
-        if (i >= d.nv) break;
-        const float r = d.R[(size_t)l * d.nv + i];
-        if (r > 0.f) {
-          const double x = d.dr[i];
-          s1 += (double)r * x;
-          s2 += (double)r * x * x;
-          st += (double)d.counts[(size_t)l * d.nv + i] * x;
+      for (uint32_t j = threadIdx.x; j < kElemPerTile / 4; j += kThreads) {
+        const uint32_t i4 = base4 + j;
+        if (i4 >= nv4) break;
+        const f4v r = gld4(d.R + (size_t)l * d.nv, i4);
+        const f4v c = gld4(d.counts + (size_t)l * d.nv, i4);
+        const f4v x = gld4(d.dr, i4);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (r[q] > 0.f) {
+            const double xq = x[q];
+            s1 += (double)r[q] * xq;
+            s2 += (double)r[q] * xq * xq;
+            st += (double)c[q] * xq;
+          }
         }
       }
       s1 = block_sum(s1, red);
