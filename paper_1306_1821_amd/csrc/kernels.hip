@@ -23,6 +23,9 @@
 #endif
 // non-temporal hints on the state in the k-space pass (HMC_XNT) and on alpha,
 // beta in the real-space pass (HMC_NT)
+#ifndef HMC_DOT_F32
+#define HMC_DOT_F32 0
+#endif
 #ifndef HMC_LDS_TAB
 #define HMC_LDS_TAB 1
 #endif
@@ -317,15 +320,25 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return red[0] + red[1] + red[2] + red[3];
 }
 
-// per-wave shell bins in LDS: bins[wave * kMaxBins + m]
-__device__ __forceinline__ void bins_zero(double* bins) {
-  for (int i = threadIdx.x; i < 4 * kMaxBins; i += kThreads) bins[i] = 0.0;
+// per-wave shell bins in LDS: bins[wave * kMaxBins + m].  HMC_DOT_F32: the
+// k-space pass accumulates its shell dot products in float per wave (flushed to
+// float64 per tile), which halves the LDS atomic traffic.
+#if HMC_DOT_F32
+typedef float bin_t;
+#else
+typedef double bin_t;
+#endif
+template <class B>
+__device__ __forceinline__ void bins_zero(B* bins) {
+  for (int i = threadIdx.x; i < 4 * kMaxBins; i += kThreads) bins[i] = (B)0;
   __syncthreads();
 }
-__device__ __forceinline__ void bins_flush(double* bins, double* dst, int nb) {
+template <class B>
+__device__ __forceinline__ void bins_flush(B* bins, double* dst, int nb) {
   __syncthreads();
   for (int m = threadIdx.x; m < nb; m += kThreads)
-    dst[m] = ((bins[m] + bins[kMaxBins + m]) + bins[2 * kMaxBins + m]) + bins[3 * kMaxBins + m];
+    dst[m] = (((double)bins[m] + (double)bins[kMaxBins + m]) + (double)bins[2 * kMaxBins + m]) +
+             (double)bins[3 * kMaxBins + m];
   __syncthreads();
 }
 
@@ -336,7 +349,7 @@ __device__ __forceinline__ void bins_flush(double* bins, double* dst, int nb) {
 // before its first use so that one wait covers them.
 template <int N, int MODE>
 __device__ __forceinline__ void xpass(const ChainDev& d, int lt, const XArgs a, const float2* __restrict__ twall,
-                      float2* lds, double* red, double* bins) {
+                      float2* lds, double* red, bin_t* bins) {
   using C = XC<N>;
   constexpr int T = C::T, B = C::B, E = N / T, H = N / 2 + 1, ES = B + 1;
   constexpr uint32_t stride = (uint32_t)N * H;
@@ -420,7 +433,7 @@ __device__ __forceinline__ void xpass(const ChainDev& d, int lt, const XArgs a, 
         const float2 x = gldi(dkb, offs(e));
         const float s = (a.flags & XF_SCALE) ? tf[kTScale + me] : 1.f;
         const double val = wz * ((double)(s * x.x) * g.x + (double)(s * x.y) * g.y);
-        atomicAdd(&bins[(threadIdx.x >> 6) * kMaxBins + me], val);
+        atomicAdd(&bins[(threadIdx.x >> 6) * kMaxBins + me], (bin_t)val);
       }
     }
   } else {
@@ -512,7 +525,7 @@ __global__ void __launch_bounds__(kThreads) k_xpass(const ChainDev* __restrict__
                                                      const float2* __restrict__ tw) {
   extern __shared__ float2 lds[];
   __shared__ double red[4];
-  __shared__ double bins[4 * kMaxBins];
+  __shared__ bin_t bins[4 * kMaxBins];
   for (TileWalk w = tile_walk(total); w.cur < w.end; w.cur += w.step) {
     const int tile = w.cur;
     const int c = find_chain(ch, nch, tile, kTileXY);
@@ -534,7 +547,7 @@ __global__ void __launch_bounds__(kThreads) k_xpass_n(const ChainDev* __restrict
                                                        const float2* __restrict__ tw) {
   extern __shared__ float2 lds[];
   __shared__ double red[4];
-  __shared__ double bins[4 * kMaxBins];
+  __shared__ bin_t bins[4 * kMaxBins];
   for (TileWalk w = tile_walk(total); w.cur < w.end; w.cur += w.step) {
     const int tile = w.cur;
     const int c = find_chain(ch, nch, tile, kTileXY);
