@@ -15,9 +15,10 @@ The JSON line also carries:
                 of the same workload (a few leapfrog steps).
 
 --workload cfg4 times the batched pattern instead: 16 independent chains (8 at
-64^3, 6 at 128^3, 2 at 192^3, each with its own mask seed and 2-4 subsamples) in
-one launch per stage, sweeps replayed from a captured HIP graph, launch shapes
-from the autotuner; `value` is chain leapfrog steps per second and the line
+64^3, 6 at 128^3, 2 at 192^3, each with its own mask seed and 2-4 subsamples)
+advancing together, sweeps replayed from a captured HIP graph, launch shapes
+from the autotuner (one fused launch over all chains per stage, or one launch
+per grid size, whichever it measures faster); `value` is chain leapfrog steps per second and the line
 also gives the 256^3-equivalent rate (voxel updates / 256^3) and split R-hat of
 ln P(k) across same-size chains over the timed sweeps.
 
@@ -152,7 +153,7 @@ def batched_main(args):
         "value": value, "unit": "chain leapfrog steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "cfg4: 16 independent chains in one launch per stage, "
+        "config": {"workload": "cfg4: 16 independent chains advancing together, "
                                "8 at 64^3 (2 subsamples), 6 at 128^3 (4), 2 at 192^3 (3), one "
                                "mask seed per chain, 30 leapfrog steps, joint move on; one "
                                "step = one sweep of every chain", "eps": args.eps_batch},

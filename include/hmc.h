@@ -179,14 +179,18 @@ hmc_status hmc_warm_start(hmc_ctx* ctx, int32_t chain, const float* mu_dev,
 
 /* Launch shape of a pass class (0: k-space x passes, 1: y passes, 2: real-space
  * z passes): grid = number of persistent workgroups that walk the tiles (a
- * multiple of 8 keeps each XCD on a contiguous run of tiles), or 0 for one
- * workgroup per tile (the default).  Results do not depend on it. */
+ * multiple of 8 keeps each XCD on a contiguous run of tiles), 0 for one
+ * workgroup per tile (the default), or -1 for one single-size launch per grid
+ * size of a mixed-size batch (one workgroup per tile each; the same as 0 when
+ * every chain has one size).  Results do not depend on it. */
 hmc_status hmc_set_launch(hmc_ctx* ctx, int32_t pass_class, int32_t grid);
 
 /* Autotuner of the launch shapes: for each pass class, times `reps` launches of
- * each candidate grid (one workgroup per tile, or 2, 3, 4, 5, 6, 8, 12
+ * each candidate (for mixed-size batches one launch per size group, then one
+ * launch over the batch with one workgroup per tile or 2, 3, 4, 5, 6, 8, 12
  * workgroups per compute unit) on the context's chains with HIP events and keeps
- * the fastest; chosen (host [3], may be NULL) receives the grids.  The state
+ * the fastest; chosen (host [3], may be NULL) receives the grids in the form
+ * hmc_set_launch takes.  The state
  * (delta_hat, p_hat, the parameters) is unchanged; captured graphs are dropped. */
 hmc_status hmc_autotune(hmc_ctx* ctx, int32_t reps, int32_t* chosen);
 

@@ -301,7 +301,8 @@ class Sampler:
         return out.cpu().numpy()
 
     def set_launch(self, pass_class, grid):
-        """Persistent workgroups for a pass class (0 x, 1 y, 2 z); 0: one per tile."""
+        """Persistent workgroups for a pass class (0 x, 1 y, 2 z); 0: one per tile;
+        -1: one launch per grid size of a mixed-size batch."""
         self._check(self.L.hmc_set_launch(self.ctx, int(pass_class), int(grid)))
 
     def autotune(self, reps=10):

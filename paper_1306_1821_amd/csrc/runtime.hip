@@ -7,6 +7,7 @@
 // the host until its statistics are copied back at the end.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -101,6 +102,16 @@ struct hmc_ctx {
   int nsteps = 0;
   int uniform_n = 0;  // N shared by every chain (0 if sizes differ)
   int max_nb = 0, max_sub = 0;
+  // batches of several grid sizes: one descriptor array per size (tile bases from
+  // zero) so that a pass class can run as one single-size launch per size group
+  struct Group {
+    int n = 0, nch = 0;
+    int total[kTileClasses] = {0, 0, 0, 0};
+    std::vector<int> members;
+    ChainDev* d = nullptr;
+  };
+  std::vector<Group> groups;
+  bool grouped[3] = {false, false, false};  // per pass class (x, y, z)
   bool learned = false;      // every chain runs the learned mass
   bool mass_mixed = false;   // some chains only have a learned mass: no trajectories
   // pass timing (hmc_timing)
@@ -179,33 +190,51 @@ struct Seq {
   const int* tot;
   hipStream_t s;
   int un;  // N shared by all chains, or 0
+  // calls f(descriptors, chains, tile totals, uniform N, grid) once for the whole
+  // batch, or once per size group when the class runs grouped
+  template <class F>
+  void each(int cls, F f) {
+    if (un == 0 && c->grouped[cls] && !c->groups.empty()) {
+      for (auto& g : c->groups) f(g.d, g.nch, g.total, g.n, 0);
+    } else {
+      f(d, nch, tot, un, c->grid[cls]);
+    }
+  }
   void x(int mode, float kick, float drift, int flags) {
     Timed tm(c, mode == X_STEP ? 0 : 3, s);
-    launch_xpass(mode, d, nch, tot[kTileXY], c->lds_x, XArgs{kick, drift, flags}, c->tw,
-                 c->grid[0], s, un);
+    each(0, [&](const ChainDev* dd, int n, const int* t, int u, int g) {
+      launch_xpass(mode, dd, n, t[kTileXY], c->lds_x, XArgs{kick, drift, flags}, c->tw, g, s, u);
+    });
     tm.done(s);
   }
   void y(int dir, int buf = 0) {
     Timed tm(c, 1, s);
-    launch_ypass(dir, d, nch, tot[kTileXY], c->lds_x, c->tw, c->grid[1], s, un, buf);
+    each(1, [&](const ChainDev* dd, int n, const int* t, int u, int g) {
+      launch_ypass(dir, dd, n, t[kTileXY], c->lds_x, c->tw, g, s, u, buf);
+    });
     tm.done(s);
   }
   void xl(int mode, float kick, float drift) {
     Timed tm(c, 3, s);
-    launch_xpass_learned(mode, d, nch, tot[kTileXY], c->lds_x, XArgs{kick, drift, 0}, c->tw,
-                         c->grid[0], s, un);
+    each(0, [&](const ChainDev* dd, int n, const int* t, int u, int g) {
+      launch_xpass_learned(mode, dd, n, t[kTileXY], c->lds_x, XArgs{kick, drift, 0}, c->tw, g,
+                           s, u);
+    });
     tm.done(s);
   }
   void zl(int mode, int flags) {
     Timed tm(c, 3, s);
-    launch_zpass_learned(mode, d, nch, tot[kTileZ], c->lds_z, ZArgs{flags, 0, nullptr}, c->tw,
-                         c->grid[2], s, un);
+    each(2, [&](const ChainDev* dd, int n, const int* t, int u, int g) {
+      launch_zpass_learned(mode, dd, n, t[kTileZ], c->lds_z, ZArgs{flags, 0, nullptr}, c->tw, g,
+                           s, u);
+    });
     tm.done(s);
   }
   void z(int mode, int flags, const float* src = nullptr) {
     Timed tm(c, mode == Z_GRAD ? 2 : 3, s);
-    launch_zpass(mode, d, nch, tot[kTileZ], c->lds_z, ZArgs{flags, 0, src}, c->tw,
-                 c->grid[2], s, un);
+    each(2, [&](const ChainDev* dd, int n, const int* t, int u, int g) {
+      launch_zpass(mode, dd, n, t[kTileZ], c->lds_z, ZArgs{flags, 0, src}, c->tw, g, s, u);
+    });
     tm.done(s);
   }
   // g_hat, delta and the data energy of the current delta_hat
@@ -241,6 +270,21 @@ static hmc_status upload_desc(hmc_ctx* c) {
     for (int j = 0; j < kTileClasses; ++j) s.tb[j] = 0;
     HIPCHK(c, hipMemcpyAsync(k.solo, &s, sizeof(ChainDev), hipMemcpyHostToDevice, c->stream));
   }
+  for (auto& g : c->groups) {
+    std::vector<ChainDev> gd;
+    int base[kTileClasses] = {0, 0, 0, 0};
+    for (int i : g.members) {
+      ChainDev s = c->ch[i].dev;
+      for (int j = 0; j < kTileClasses; ++j) {
+        s.tb[j] = base[j];
+        base[j] += s.nt[j];
+      }
+      gd.push_back(s);
+    }
+    HIPCHK(c, hipMemcpyAsync(g.d, gd.data(), gd.size() * sizeof(ChainDev), hipMemcpyHostToDevice,
+                             c->stream));
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
   return HMC_OK;
 }
 
@@ -342,6 +386,7 @@ void hmc_destroy(hmc_ctx* ctx) {
     (void)hipFree(k.solo);
   }
   (void)hipFree(ctx->d_all);
+  for (auto& g : ctx->groups) (void)hipFree(g.d);
   (void)hipFree(ctx->tw);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   delete ctx;
@@ -492,6 +537,26 @@ hmc_status hmc_init_batch(const hmc_config* cfg, const hmc_buffers* buf, int32_t
   if (hipMalloc(&c->d_all, n_chains * sizeof(ChainDev)) != hipSuccess) {
     c->err = "hipMalloc descriptors";
     return bail(HMC_EDEVICE);
+  }
+  if (c->uniform_n == 0) {
+    for (int i = 0; i < n_chains; ++i) {
+      const int n = c->ch[i].cfg.n;
+      auto it = std::find_if(c->groups.begin(), c->groups.end(),
+                             [n](const hmc_ctx::Group& g) { return g.n == n; });
+      if (it == c->groups.end()) {
+        c->groups.emplace_back();
+        it = c->groups.end() - 1;
+        it->n = n;
+      }
+      it->members.push_back(i);
+      it->nch += 1;
+      for (int j = 0; j < kTileClasses; ++j) it->total[j] += c->ch[i].dev.nt[j];
+    }
+    for (auto& g : c->groups)
+      if (hipMalloc(&g.d, g.nch * sizeof(ChainDev)) != hipSuccess) {
+        c->err = "hipMalloc group descriptors";
+        return bail(HMC_EDEVICE);
+      }
   }
   hmc_status st;
   for (auto& k : c->ch)
@@ -857,8 +922,9 @@ static void drop_graphs(hmc_ctx* c) {
 static int class_tiles(hmc_ctx* c, int cls) { return c->total[cls == 2 ? kTileZ : kTileXY]; }
 
 hmc_status hmc_set_launch(hmc_ctx* c, int32_t cls, int32_t grid) {
-  if (!c || cls < 0 || cls > 2 || grid < 0) return fail(c, HMC_EINVAL, "bad argument");
-  c->grid[cls] = grid >= class_tiles(c, cls) ? 0 : grid;
+  if (!c || cls < 0 || cls > 2 || grid < -1) return fail(c, HMC_EINVAL, "bad argument");
+  c->grouped[cls] = grid == -1 && !c->groups.empty();
+  c->grid[cls] = grid < 0 || grid >= class_tiles(c, cls) ? 0 : grid;
   drop_graphs(c);
   return HMC_OK;
 }
@@ -892,9 +958,14 @@ hmc_status hmc_autotune(hmc_ctx* c, int32_t reps, int32_t* chosen) {
   for (int cls = 0; cls < 3 && st == HMC_OK; ++cls) {
     float best = 0.f;
     int best_grid = 0;
-    for (int m : mult) {
-      const int grid = m * cus;
-      if (m > 0 && (grid >= class_tiles(c, cls) || grid % 8 != 0)) continue;
+    bool best_grouped = false;
+    // candidates: one launch per size group (batches of several sizes), then one
+    // launch over the whole batch with each grid
+    for (int cand = c->groups.empty() ? 0 : -1; cand < (int)(sizeof(mult) / sizeof(int)); ++cand) {
+      const bool grp = cand < 0;
+      const int grid = grp ? 0 : mult[cand] * cus;
+      if (!grp && mult[cand] > 0 && (grid >= class_tiles(c, cls) || grid % 8 != 0)) continue;
+      c->grouped[cls] = grp;
       c->grid[cls] = grid;
       tune_launch(c, cls);  // warm-up
       if (hipEventRecord(a, c->stream) != hipSuccess) { st = HMC_EDEVICE; break; }
@@ -908,10 +979,12 @@ hmc_status hmc_autotune(hmc_ctx* c, int32_t reps, int32_t* chosen) {
       if (best == 0.f || ms < best) {
         best = ms;
         best_grid = grid;
+        best_grouped = grp;
       }
     }
     c->grid[cls] = best_grid;
-    if (chosen) chosen[cls] = best_grid;
+    c->grouped[cls] = best_grouped;
+    if (chosen) chosen[cls] = best_grouped ? -1 : best_grid;
   }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
