@@ -207,17 +207,12 @@ def learned_main(args):
                                f"({args.mocks} mocks x 31), applied to the 256^3 survey "
                                "(L=1500 Mpc/h, 6 subsamples, 60 shells, joint move on); "
                                "4 chains per mass, warm-started, one step = one sweep"},
-        "plain": {"median_ess_per_s": float(np.median(pl["ess_per_s"])),
-                  "min_ess_per_s": float(pl["ess_per_s"].min()),
-                  "max_rhat": float(pl["rhat"].max()),
-                  "shells_rhat_below_1.01": int((pl["rhat"] < 1.01).sum()),
-                  "eps": pl["eps"], "acceptance": pl["acceptance"],
-                  "ms_per_sweep": pl["ms_per_sweep"]},
-        "learned": {"median_ess_per_s": value, "min_ess_per_s": float(le["ess_per_s"].min()),
-                    "max_rhat": float(le["rhat"].max()),
-                    "shells_rhat_below_1.01": int((le["rhat"] < 1.01).sum()),
-                    "eps": le["eps"], "acceptance": le["acceptance"],
-                    "ms_per_sweep": le["ms_per_sweep"]},
+        "plain": dict(learned.ess_table(pl), eps=pl["eps"], acceptance=pl["acceptance"],
+                      ms_per_sweep=pl["ms_per_sweep"],
+                      data_dominated=learned.ess_table(pl, learned.data_dominated_shells(mk))),
+        "learned": dict(learned.ess_table(le), eps=le["eps"], acceptance=le["acceptance"],
+                        ms_per_sweep=le["ms_per_sweep"],
+                        data_dominated=learned.ess_table(le, learned.data_dominated_shells(mk))),
         "ratio_median_ess_per_s": value / float(np.median(pl["ess_per_s"])),
         "burn_in_sweeps": {k: {"potential": int(r["burn_pot"]), "ln_P": int(r["burn_logbias"])}
                            for k, r in burn.items()},
@@ -254,7 +249,7 @@ def main():
         sys.exit(2)
     if args.learned:
         if args.steps == 20:
-            args.steps = 600
+            args.steps = 1500
         return learned_main(args)
     if args.workload == "cfg4":
         return batched_main(args)

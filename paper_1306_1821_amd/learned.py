@@ -190,6 +190,15 @@ def pk_ess_summary(pk, wall):
     return dict(ess=ess, ess_per_s=ess / wall, rhat=rhat, wall=wall)
 
 
+def ess_table(r, shells=None):
+    """Median / min ESS/s and max split R-hat over the given shells (all if None)."""
+    sel = np.arange(len(r["ess"])) if shells is None else np.asarray(shells)
+    return dict(median_ess_per_s=float(np.median(r["ess_per_s"][sel])),
+                min_ess_per_s=float(r["ess_per_s"][sel].min()),
+                max_rhat=float(r["rhat"][sel].max()),
+                shells_rhat_below_1_01=int((r["rhat"][sel] < 1.01).sum()), shells=int(sel.size))
+
+
 def warm_up(sampler, trajs, first_index=2 << 30):
     """Bare trajectories under the starting P, b and Nbar before the first sweep:
     the density settles given the spectrum before P is first redrawn from it
@@ -302,9 +311,10 @@ def ess_study(mk, mu, lv, chains=4, burn=100, sweeps=600, target=0.8, eps0=None,
                  ms_per_sweep=1e3 * wall / sweeps)
         out[name] = r
         if log:
+            dd = ess_table(r, data_dominated_shells(mk))
             log(f"ESS {name}: eps {eps:.4f}, acceptance {r['acceptance']:.2f}, {r['ms_per_sweep']:.1f} "
                 f"ms/sweep; ESS/s median {np.median(r['ess_per_s']):.3g} min {r['ess_per_s'].min():.3g}; "
                 f"R-hat max {r['rhat'].max():.3f}, shells with R-hat < 1.01: "
-                f"{int((r['rhat'] < 1.01).sum())}/{len(r['rhat'])}")
+                f"{int((r['rhat'] < 1.01).sum())}/{len(r['rhat'])}; data-dominated shells: {dd}")
     return out
 

@@ -115,3 +115,21 @@ def test_launch_shapes_do_not_change_results(names):
         for sw_a, sw_b in zip(pk, finals[0][1]):
             for a, b in zip(sw_a, sw_b):
                 assert np.array_equal(a, b)
+
+
+def test_set_step_equals_configured_step():
+    """hmc_set_step gives the same trajectories as a context configured with that eps."""
+    m = mock("cfg1")
+    a = Sampler([chain_spec(m, eps=0.03, nsteps=8, seed=3)])
+    b = Sampler([chain_spec(m, eps=0.07, nsteps=8, seed=3)])
+    for s in (a, b):
+        s.set_state(0, start_state(m)[0])
+    b.set_step(0, 0.03)
+    for i in range(3):
+        ra, rb = a.trajectory(i), b.trajectory(i)
+        assert ra[0][0] == rb[0][0] and ra[1][0] == rb[1][0]
+    assert np.array_equal(a.state(0)["delta_k"], b.state(0)["delta_k"])
+    with pytest.raises(Exception):
+        b.set_step(0, -1.0)
+    a.close()
+    b.close()
