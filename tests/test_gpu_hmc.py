@@ -93,7 +93,7 @@ def test_hamiltonian_on_identical_arrays(n, box, nb):
 
 
 TRAJ_CASES = [("tiny8x2", 0.1, 10), ("small16", 0.1, 10), ("cfg1", 0.05, 20), (64, 0.05, 10),
-              (128, 0.04, 8)]
+              (128, 0.04, 8), ("cfg3", 0.02, 4)]     # cfg3: the 256^3 bench workload
 
 
 def traj_mock(case):
@@ -111,7 +111,7 @@ def test_trajectory_matches_oracle(case, eps, nsteps):
     s.set_coefficients(0, a32, b32)
     d32, dk = start_state(mk)
     s.set_state(0, d32)
-    post = oracle_posterior(mk, a32, b32, workers=4)
+    post = oracle_posterior(mk, a32, b32, workers=8)
     for traj in range(2):
         before = s.state(0)
         dH, acc = s.trajectory(traj)

@@ -13,7 +13,8 @@ if not torch.cuda.is_available():
 
 from paper_1306_1821_amd.binding import Sampler  # noqa: E402
 
-CASES = [("tiny8x2", 0.1, 8), ("small16", 0.08, 10), ("cfg1", 0.05, 12), (64, 0.04, 8)]
+CASES = [("tiny8x2", 0.1, 8), ("small16", 0.08, 10), ("cfg1", 0.05, 12), (64, 0.04, 8),
+         ("cfg3", 0.02, 3)]     # cfg3: the 256^3 bench workload
 
 
 def case_mock(c):
@@ -31,7 +32,7 @@ def test_learned_trajectory_matches_oracle(case, eps, nsteps):
     s.set_coefficients(0, a32, b32)
     s.set_state(0, start_state(mk)[0])
     s.set_mass(0, logvar)
-    post = oracle_posterior(mk, a32, b32, workers=4)
+    post = oracle_posterior(mk, a32, b32, workers=8)
     sqrtD = hmc.mass_factor(logvar.astype(np.float64))
     for traj in range(2):
         before = s.state(0)
@@ -57,7 +58,7 @@ def test_learned_trajectory_matches_oracle(case, eps, nsteps):
     s.close()
 
 
-@pytest.mark.parametrize("case", ["small16", "cfg1", 64])
+@pytest.mark.parametrize("case", ["small16", "cfg1", 64, "cfg3"])
 def test_warm_start_matches_oracle(case):
     mk = case_mock(case)
     n = mk["cfg"].n
@@ -72,7 +73,7 @@ def test_warm_start_matches_oracle(case):
         st = s.state(0)
         ref = hmc.warm_start(mu.astype(np.float64), lv.astype(np.float64), post, 77, 3, draw)
         e_k = rel_l2(st["delta_k"], ref)
-        e_r = rel_l2(st["delta_r"], np.fft.irfftn(ref, s=(n, n, n), norm="ortho"))
+        e_r = rel_l2(st["delta_r"], np.fft.irfftn(ref, s=(n, n, n), axes=(0, 1, 2), norm="ortho"))
         print(f"N={n} draw {draw}: delta_hat rel-L2 {e_k:.2e}, delta rel-L2 {e_r:.2e}")
         assert e_k < 1e-5 and e_r < 1e-5
     s.close()
