@@ -79,6 +79,12 @@ typedef struct hmc_config {
   int32_t rj_move;           /* 1: run the joint (P, delta) move in gibbs_sweep */
   double rj_log_bound;       /* joint move keeps ln lambda within +-bound of its
                                 value at init (reflecting walls); 0 -> 10 */
+  int32_t tau_mode;          /* 0: every trajectory runs n_leapfrog steps; 1: the
+                                pseudo-time is drawn uniformly (Sec. "The HMC
+                                algorithm"): n ~ U{1..n_leapfrog} per trajectory /
+                                sweep from Philox stream 10 of the first chain at
+                                the trajectory / sweep index, shared by all chains
+                                of a context and by the joint move of that sweep */
 } hmc_config;
 
 /* Caller-owned device buffers of one chain. */
@@ -165,7 +171,7 @@ hmc_status hmc_set_state(hmc_ctx* ctx, int32_t chain, const float* delta_r_dev);
 /* Warm start from a predicted posterior mean mu and log-variance s (device
  * [N][N][N] float32 each, e.g. from cnn_forward): the state becomes
  *   delta = mu + sqrt(exp(s) / sigma^2) xi,   xi = F^-1(sqrt(lambda_k) F w),
- * w white noise from Philox stream 10 at draw index `draw_index` (low 32 bits),
+ * w white noise from Philox stream 11 at draw index `draw_index` (low 32 bits),
  * lambda_k the chain's current prior eigenvalues (k = 0 excluded) and
  * sigma^2 = N^-3 sum_{k != 0} lambda_k the prior variance per voxel, i.e. a prior
  * draw rescaled to the predicted variance and shifted to the predicted mean.

@@ -184,13 +184,18 @@ def sweep(state, data, cfg, s):
     """One block sweep.  state: dict(dk, pk, bias, nbar); returns the new state.
 
     cfg: n, box, nb, eps, nsteps, alpha_prior, seed, chain, fixed_mask, rj (bool),
-    and, if rj, lam_lo / lam_hi bounds of the joint move.
+    and, if rj, lam_lo / lam_hi bounds of the joint move; optional tau_mode (the
+    step count of the sweep's trajectory and joint move drawn by hmc.draw_steps
+    from the Philox stream of chain tau_chain, default this chain).
     """
     from . import rj
     n, box, nb = cfg["n"], cfg["box"], cfg["nb"]
     R, counts = data["R"], data["counts"]
     dk, pk, bias, nbar = state["dk"], state["pk"], state["bias"], state["nbar"]
     post = hmc.make_posterior(n, box, nb, pk, R, counts, bias, nbar, cfg.get("workers", 1))
+    if cfg.get("tau_mode", False):
+        cfg = dict(cfg, nsteps=hmc.draw_steps(cfg["nsteps"], cfg["seed"],
+                                              cfg.get("tau_chain", cfg["chain"]), s))
     tr = hmc.trajectory(dk, post, cfg["eps"], cfg["nsteps"], cfg["seed"], cfg["chain"], s)
     dk = tr["state"]
     n_modes = grid.mode_counts(n, nb)

@@ -81,6 +81,14 @@ def leapfrog(dk, pk, post, eps, nsteps):
     return dk, pk, gk, delta
 
 
+def draw_steps(n_max, seed, chain, traj):
+    """Uniformly drawn pseudo-time (text after eq. HAMILTON2_a: tau is drawn from a
+    uniform distribution): n = 1 + floor(u n_max), u from Philox stream 10, so that
+    tau = n eps is uniform on {eps, 2 eps, ..., n_max eps}."""
+    u = philox.uniform(seed, chain, philox.STREAM_TAU, traj)
+    return min(n_max, 1 + int(u * n_max))
+
+
 def trajectory(dk, post, eps, nsteps, seed, chain, traj):
     """One HMC proposal + accept.  Returns a dict with the new state and dH."""
     pk0 = draw_momentum(post, seed, chain, traj)
@@ -165,7 +173,7 @@ def trajectory_learned(dk, post, sqrtD, eps, nsteps, seed, chain, traj):
 
 
 def prior_draw(post, seed, chain, draw):
-    """xi = F^-1(sqrt(lambda_k) F w), w ~ N(0, 1) per voxel from Philox stream 10:
+    """xi = F^-1(sqrt(lambda_k) F w), w ~ N(0, 1) per voxel from Philox stream 11:
     a draw from the Gaussian prior S (eq. Wiener_Posterior_psi's first term)."""
     n = post.n
     sel = post.shells >= 0

@@ -36,7 +36,8 @@ STREAM_GIG = 6
 STREAM_BIAS = 7
 STREAM_RJ_MOMENTA = 8
 STREAM_RJ_ACCEPT = 9
-STREAM_WARM = 10
+STREAM_TAU = 10
+STREAM_WARM = 11
 
 
 def philox4x32_10(c0, c1, c2, c3, k0, k1):

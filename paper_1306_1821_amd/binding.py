@@ -22,7 +22,7 @@ class HmcConfig(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("chain_id", ctypes.c_uint32),
                 ("n_leapfrog", ctypes.c_int32), ("eps", ctypes.c_double),
                 ("fixed_bias_mask", ctypes.c_uint32), ("rj_move", ctypes.c_int32),
-                ("rj_log_bound", ctypes.c_double)]
+                ("rj_log_bound", ctypes.c_double), ("tau_mode", ctypes.c_int32)]
 
 
 class HmcBuffers(ctypes.Structure):
@@ -126,8 +126,8 @@ class Sampler:
 
     chains: list of dicts with keys n, box, nb, R [c,N,N,N], counts [c,N,N,N]
     (numpy or torch), bias [c], nbar [c], pk [nb] (Mpc/h)^3, and optional
-    seed, chain_id, nsteps, eps, alpha_prior, fixed_mask, rj, delta_k0
-    (complex [N,N,N/2+1]).
+    seed, chain_id, nsteps, eps, alpha_prior, fixed_mask, rj, rj_log_bound,
+    tau_mode, delta_k0 (complex [N,N,N/2+1]).
     """
 
     def __init__(self, chains, device="cuda:0", stream=None):
@@ -152,6 +152,7 @@ class Sampler:
             cfg.fixed_bias_mask = int(c.get("fixed_mask", 1))
             cfg.rj_move = int(bool(c.get("rj", False)))
             cfg.rj_log_bound = float(c.get("rj_log_bound", 10.0))
+            cfg.tau_mode = int(bool(c.get("tau_mode", False)))
             wb = self.L.hmc_workspace_bytes(ctypes.byref(cfg))
             if wb == 0:
                 raise HmcError(-1, f"invalid configuration for chain {i}")

@@ -676,7 +676,7 @@ __device__ __forceinline__ void zpass(const ChainDev& d, int lt, const ZArgs a, 
 #pragma unroll
     for (int e = 0; e < E; ++e)
       v[e] = gldi(reinterpret_cast<const float2*>(a.src), ro + t + T * e);
-  } else {  // Z_NOISE: white noise w_i from Philox stream 3 (10: warm start), element = voxel index
+  } else {  // Z_NOISE: white noise w_i from Philox stream 3 (11: warm start), element = voxel index
     const uint32_t stream = (a.flags & ZF_WARM) ? hmcrng::kWarm : hmcrng::kMomenta;
 #pragma unroll
     for (int e = 0; e < E; ++e) {

@@ -18,7 +18,8 @@ enum Stream : uint32_t {
   kBias = 7,
   kRjMomenta = 8,
   kRjAccept = 9,
-  kWarm = 10,
+  kTau = 10,
+  kWarm = 11,
 };
 
 struct U4 {

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -17,6 +18,7 @@
 #include "../../include/hmc.h"
 #include "common.hpp"
 #include "kernels.hpp"
+#include "rng.hpp"
 
 using namespace hmc;
 
@@ -99,7 +101,9 @@ struct hmc_ctx {
   int total[kTileClasses] = {0, 0, 0, 0};
   int lds_x = 0, lds_z = 0;
   int grid[3] = {0, 0, 0};  // launch grid per pass class (x, y, z); 0: one workgroup per tile
-  int nsteps = 0;
+  int nsteps = 0;      // n_leapfrog (the maximum when tau_mode draws the step count)
+  int cur_steps = 0;   // steps of the current trajectory / sweep
+  int tau_mode = 0;
   int uniform_n = 0;  // N shared by every chain (0 if sizes differ)
   int max_nb = 0, max_sub = 0;
   // batches of several grid sizes: one descriptor array per size (tile bases from
@@ -125,7 +129,7 @@ struct hmc_ctx {
   bool use_graph = false;
   hipStream_t gstream = nullptr;
   hipEvent_t gev_a = nullptr, gev_b = nullptr;
-  hipGraphExec_t g_traj = nullptr, g_sweep = nullptr;
+  std::map<int, hipGraphExec_t> g_traj, g_sweep;  // captured per step count
   std::string err;
   std::vector<double> stat_pk, stat_bias, stat_nbar;
 };
@@ -316,6 +320,17 @@ static hmc_status run_sweep(hmc_ctx* c);
 
 // Capture `body` once on the library's side stream and replay the graph; the
 // side stream is ordered after and before the caller's stream with events.
+// leapfrog steps of a trajectory / sweep: n_leapfrog, or with tau_mode a uniform
+// draw from 1..n_leapfrog (the paper's uniformly drawn pseudo-time tau = n eps)
+// from Philox stream 10 of the first chain at the trajectory / sweep index
+static int steps_of(hmc_ctx* c, uint64_t index) {
+  if (!c->tau_mode) return c->nsteps;
+  const hmc_config& f = c->ch[0].cfg;
+  const hmcrng::U4 w = hmcrng::block(f.seed, f.chain_id, hmcrng::kTau, (uint32_t)index, 0, 0);
+  const int n = 1 + (int)(hmcrng::uniform(w.w[0]) * c->nsteps);
+  return n > c->nsteps ? c->nsteps : n;
+}
+
 static hmc_status run_graph(hmc_ctx* c, hipGraphExec_t* exec, hmc_status (*body)(hmc_ctx*)) {
   if (!c->gstream) {
     HIPCHK(c, hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking));
@@ -373,8 +388,8 @@ void hmc_destroy(hmc_ctx* ctx) {
     (void)hipEventDestroy(u.second.second);
   }
   for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
-  if (ctx->g_traj) (void)hipGraphExecDestroy(ctx->g_traj);
-  if (ctx->g_sweep) (void)hipGraphExecDestroy(ctx->g_sweep);
+  for (auto& g : ctx->g_traj) (void)hipGraphExecDestroy(g.second);
+  for (auto& g : ctx->g_sweep) (void)hipGraphExecDestroy(g.second);
   if (ctx->gev_a) (void)hipEventDestroy(ctx->gev_a);
   if (ctx->gev_b) (void)hipEventDestroy(ctx->gev_b);
   if (ctx->gstream) (void)hipStreamDestroy(ctx->gstream);
@@ -404,6 +419,8 @@ hmc_status hmc_init_batch(const hmc_config* cfg, const hmc_buffers* buf, int32_t
     if (!valid_cfg(&cfg[i], &why)) return fail(nullptr, HMC_EINVAL, why);
     if (cfg[i].n_leapfrog != cfg[0].n_leapfrog)
       return fail(nullptr, HMC_EINVAL, "all chains of a batch need the same n_leapfrog");
+    if (cfg[i].tau_mode != cfg[0].tau_mode)
+      return fail(nullptr, HMC_EINVAL, "all chains of a batch need the same tau_mode");
     const hmc_buffers& b = buf[i];
     if (!b.R || !b.counts || !b.delta_k || !b.mom_k || !b.grad_k || !b.delta_r || !b.alpha ||
         !b.beta || !b.work)
@@ -413,7 +430,8 @@ hmc_status hmc_init_batch(const hmc_config* cfg, const hmc_buffers* buf, int32_t
   }
   hmc_ctx* c = new hmc_ctx();
   c->stream = (hipStream_t)stream;
-  c->nsteps = cfg[0].n_leapfrog;
+  c->nsteps = c->cur_steps = cfg[0].n_leapfrog;
+  c->tau_mode = cfg[0].tau_mode;
   c->ch.resize(n_chains);
   auto bail = [&](hmc_status st) {
     g_err = c->err;
@@ -610,8 +628,8 @@ static hmc_status run_trajectory_learned(hmc_ctx* c) {
   launch_reduce_slot(c->d_all, nch, kPartPri, kPi0, kTileXY, c->stream);
   force(0);
   q.xl(L_KICK, 0.5f, 0.f);
-  for (int s = 1; s <= c->nsteps; ++s) {
-    const bool last = s == c->nsteps;
+  for (int s = 1; s <= c->cur_steps; ++s) {
+    const bool last = s == c->cur_steps;
     q.y(-1, 1);
     q.zl(LZ_VEL, 0);
     q.y(+1, 1);
@@ -636,7 +654,7 @@ static hmc_status run_trajectory(hmc_ctx* c) {
   q.x(X_START, 0.5f, 1.f, 0);
   launch_reduce_slot(c->d_all, nch, kPartKin, kK0, kTileXY, c->stream);
   launch_reduce_slot(c->d_all, nch, kPartPri, kPi0, kTileXY, c->stream);
-  for (int s = 1; s < c->nsteps; ++s) {
+  for (int s = 1; s < c->cur_steps; ++s) {
     q.y(-1);
     q.z(Z_GRAD, 0);
     q.y(+1);
@@ -659,7 +677,9 @@ hmc_status leapfrog_trajectory(hmc_ctx* c, uint64_t traj_index, double* dH, int3
   if (c->mass_mixed)
     return fail(c, HMC_EUNSUPPORTED, "learned mass set on some chains of the context only");
   launch_set_draw(c->d_draw, (uint32_t)traj_index, c->stream);
-  hmc_status st = c->use_graph ? run_graph(c, &c->g_traj, run_trajectory) : run_trajectory(c);
+  c->cur_steps = steps_of(c, traj_index);
+  hmc_status st = c->use_graph ? run_graph(c, &c->g_traj[c->cur_steps], run_trajectory)
+                               : run_trajectory(c);
   if (st != HMC_OK) return st;
   if ((st = pull_params(c)) != HMC_OK) return st;
   bool numeric = false;
@@ -727,8 +747,8 @@ static hmc_status run_sweep(hmc_ctx* c) {
     q.y(+1);
     q.x(X_FWD, 0.f, 0.f, XF_DOT | XF_NOSTORE);
     launch_rj(RJ_BEGIN, c->d_all, nch, c->max_nb, c->stream);
-    for (int i = 0; i < c->nsteps; ++i) {
-      const bool last = i == c->nsteps - 1;
+    for (int i = 0; i < c->cur_steps; ++i) {
+      const bool last = i == c->cur_steps - 1;
       q.gradient(last ? (ZF_WRITE_DRN | ZF_DATA) : 0,
                  XF_SCALE | XF_DOT | (last ? XF_OUT_ALT : XF_NOSTORE));
       if (!last) {
@@ -755,7 +775,8 @@ hmc_status gibbs_sweep(hmc_ctx* c, uint64_t sweep_index, hmc_sweep_stats* out) {
   if (c->mass_mixed)
     return fail(c, HMC_EUNSUPPORTED, "learned mass set on some chains of the context only");
   launch_set_draw(c->d_draw, (uint32_t)sweep_index, c->stream);
-  hmc_status st = c->use_graph ? run_graph(c, &c->g_sweep, run_sweep) : run_sweep(c);
+  c->cur_steps = steps_of(c, sweep_index);
+  hmc_status st = c->use_graph ? run_graph(c, &c->g_sweep[c->cur_steps], run_sweep) : run_sweep(c);
   if (st != HMC_OK) return st;
   if ((st = pull_params(c)) != HMC_OK) return st;
   c->stat_pk.clear();
@@ -914,9 +935,10 @@ hmc_status hmc_use_graph(hmc_ctx* c, int32_t enable) {
 }
 
 static void drop_graphs(hmc_ctx* c) {
-  if (c->g_traj) (void)hipGraphExecDestroy(c->g_traj);
-  if (c->g_sweep) (void)hipGraphExecDestroy(c->g_sweep);
-  c->g_traj = c->g_sweep = nullptr;
+  for (auto& g : c->g_traj) (void)hipGraphExecDestroy(g.second);
+  for (auto& g : c->g_sweep) (void)hipGraphExecDestroy(g.second);
+  c->g_traj.clear();
+  c->g_sweep.clear();
 }
 
 static int class_tiles(hmc_ctx* c, int cls) { return c->total[cls == 2 ? kTileZ : kTileXY]; }
@@ -1068,9 +1090,10 @@ hmc_status hmc_set_mass(hmc_ctx* c, int32_t chain, const float* logvar_dev) {
   c->learned = all;
   c->mass_mixed = any && !all;
   // captured graphs hold the old pass sequence
-  if (c->g_traj) (void)hipGraphExecDestroy(c->g_traj);
-  if (c->g_sweep) (void)hipGraphExecDestroy(c->g_sweep);
-  c->g_traj = c->g_sweep = nullptr;
+  for (auto& g : c->g_traj) (void)hipGraphExecDestroy(g.second);
+  for (auto& g : c->g_sweep) (void)hipGraphExecDestroy(g.second);
+  c->g_traj.clear();
+  c->g_sweep.clear();
   return HMC_OK;
 }
 

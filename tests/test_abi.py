@@ -52,7 +52,7 @@ def _cfg(**kw):
     c = binding.HmcConfig()
     c.n, c.box, c.n_sub, c.n_bins = 32, 500.0, 1, 16
     c.alpha_prior, c.seed, c.chain_id, c.n_leapfrog, c.eps = 1.0, 1, 0, 20, 0.05
-    c.fixed_bias_mask, c.rj_move, c.rj_log_bound = 1, 0, 10.0
+    c.fixed_bias_mask, c.rj_move, c.rj_log_bound, c.tau_mode = 1, 0, 10.0, 0
     for k, v in kw.items():
         setattr(c, k, v)
     return c

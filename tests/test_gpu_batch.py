@@ -133,3 +133,28 @@ def test_set_step_equals_configured_step():
         b.set_step(0, -1.0)
     a.close()
     b.close()
+
+
+def test_drawn_step_counts_with_graphs():
+    """With tau_mode the step count varies per trajectory; graph replay (one graph per
+    step count) equals direct launches, and a batch of chains shares the draw."""
+    mks = [mock("small16"), mock("cfg1")]
+    specs = [chain_spec(m, eps=0.05, nsteps=12, seed=29, chain_id=i, rj=True, tau_mode=True)
+             for i, m in enumerate(mks)]
+    runs = []
+    for graph in (False, True):
+        s = Sampler(specs)
+        for i, m in enumerate(mks):
+            s.set_state(i, start_state(m)[0])
+        s.use_graph(graph)
+        out = [s.trajectory(100 + t) for t in range(4)] + [s.sweep(t) for t in range(4)]
+        runs.append((out, [s.state(i)["delta_k"] for i in range(2)]))
+        s.close()
+    for a, b in zip(runs[0][0], runs[1][0]):
+        if isinstance(a, tuple):
+            assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+        else:
+            for x, y in zip(a, b):
+                assert x["dH"] == y["dH"] and np.array_equal(x["pk"], y["pk"])
+    for x, y in zip(runs[0][1], runs[1][1]):
+        assert np.array_equal(x, y)

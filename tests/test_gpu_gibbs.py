@@ -24,7 +24,8 @@ def oracle_cfg(mk, spec):
 
 
 CASES = [("tiny8x2", False, 0.1, 8), ("small16", False, 0.08, 10), ("small16", True, 0.08, 10),
-         ("cfg1", False, 0.05, 20), ("cfg1", True, 0.05, 20), (64, True, 0.04, 10)]
+         ("cfg1", False, 0.05, 20), ("cfg1", True, 0.05, 20), (64, True, 0.04, 10),
+         ("small16", "tau", 0.08, 12)]     # drawn step counts, joint move on
 
 
 def case_mock(name):
@@ -34,14 +35,16 @@ def case_mock(name):
 @pytest.mark.parametrize("name,rj,eps,nsteps", CASES)
 def test_sweeps_match_oracle(name, rj, eps, nsteps):
     mk = case_mock(name)
-    spec = chain_spec(mk, eps=eps, nsteps=nsteps, seed=23, rj=rj, fixed_mask=1)
+    tau = rj == "tau"
+    rj = bool(rj)
+    spec = chain_spec(mk, eps=eps, nsteps=nsteps, seed=23, rj=rj, fixed_mask=1, tau_mode=tau)
     s = Sampler([spec])
     d32, dk = start_state(mk)
     s.set_state(0, d32)
-    ocfg = oracle_cfg(mk, spec)
+    ocfg = dict(oracle_cfg(mk, spec), tau_mode=tau)
     data = dict(R=mk["R"].astype(np.float64), counts=mk["counts"].astype(np.float64))
     state = dict(dk=dk, pk=mk["pk_init"].copy(), bias=mk["bias"].copy(), nbar=mk["nbar"].copy())
-    for sw in range(3):
+    for sw in range(5 if tau else 3):
         g = s.sweep(sw)[0]
         o = gibbs.sweep(state, data, ocfg, sw)
         print(f"{name} rj={rj} sweep {sw}: dH {g['dH']:.5e}/{o['dH']:.5e} acc {g['accepted']}/"

@@ -250,3 +250,16 @@ def test_warm_start_mean_and_variance():
     ratio = D.var(axis=0) / v
     assert abs(ratio.mean() - 1.0) < 0.05
     assert np.corrcoef(D.var(axis=0).ravel(), v.ravel())[0, 1] > 0.9
+
+
+def test_drawn_step_counts_are_uniform():
+    """n = 1 + floor(u n_max) covers 1..n_max with equal frequency (chi-square)."""
+    from scipy import stats
+    n_max, K = 12, 6000
+    draws = np.array([hmc.draw_steps(n_max, 7, 3, t) for t in range(K)])
+    assert draws.min() == 1 and draws.max() == n_max
+    counts = np.bincount(draws, minlength=n_max + 1)[1:]
+    assert stats.chisquare(counts).pvalue > 1e-3
+    # different chains and streams give different sequences
+    other = np.array([hmc.draw_steps(n_max, 7, 4, t) for t in range(200)])
+    assert np.mean(other != draws[:200]) > 0.8
