@@ -145,6 +145,14 @@ hmc_status hmc_init_batch(const hmc_config* cfg, const hmc_buffers* buf, int32_t
  * dH, accepted: host pointers with one entry per chain. */
 hmc_status leapfrog_trajectory(hmc_ctx* ctx, uint64_t traj_index, double* dH, int32_t* accepted);
 
+/* leapfrog_trajectory without a host round trip: dH_dev (device [n_chains]
+ * float64) and accepted_dev (device [n_chains] int32) receive the results in
+ * stream order; nothing is synchronised, so calls can be queued back to back or
+ * captured by the caller.  A non-finite dH is rejected on the device (no
+ * HMC_ENUMERIC report). */
+hmc_status leapfrog_trajectory_async(hmc_ctx* ctx, uint64_t traj_index, double* dH_dev,
+                                     int32_t* accepted_dev);
+
 /* Energies of eq. Hamiltonian for chain `chain` on the current buffers
  * (float64 accumulation): out[0] kinetic 1/2 sum_k |p_hat|^2/m_k from mom_k,
  * out[1] prior 1/2 sum_k |delta_hat|^2/lambda_k from delta_k, out[2] data
@@ -163,6 +171,16 @@ hmc_status shell_power(hmc_ctx* ctx, int32_t chain, double* sigma, int64_t* n_mo
  * draw of the sweep; as for trajectories, a chain must not repeat an index.
  * out: host [n_chains]. */
 hmc_status gibbs_sweep(hmc_ctx* ctx, uint64_t sweep_index, hmc_sweep_stats* out);
+
+/* Doubles of the per-sweep record gibbs_sweep_async writes, summed over chains:
+ * for each chain, in order, [dH, accepted (0/1), rj_dH, rj_accepted, status
+ * (0 ok, nonzero: a draw or energy was not finite), P_m (n_bins values,
+ * (Mpc/h)^3), b_l (c values), Nbar_l (c values)]. */
+size_t hmc_sweep_record_doubles(const hmc_ctx* ctx);
+
+/* gibbs_sweep without a host round trip: stats_dev (device float64,
+ * hmc_sweep_record_doubles values) receives the records in stream order. */
+hmc_status gibbs_sweep_async(hmc_ctx* ctx, uint64_t sweep_index, double* stats_dev);
 
 /* Replace the density state of chain `chain` with a real field (device
  * [N][N][N] float32), e.g. a warm start; the mean is removed. */

@@ -42,6 +42,7 @@ class HmcSweepStats(ctypes.Structure):
 
 
 EXPORTS = ["hmc_workspace_bytes", "hmc_init", "hmc_init_batch", "leapfrog_trajectory",
+           "leapfrog_trajectory_async", "gibbs_sweep_async", "hmc_sweep_record_doubles",
            "hamiltonian", "shell_power", "gibbs_sweep", "hmc_set_state", "hmc_set_params",
            "hmc_set_step", "hmc_warm_start", "hmc_set_launch", "hmc_autotune", "hmc_set_coefficients", "hmc_get_params", "hmc_shell_index", "hmc_set_mass",
            "hmc_timing", "hmc_use_graph", "hmc_last_error", "hmc_destroy",
@@ -72,6 +73,10 @@ def lib(path=LIB_PATH):
                                  D, P, ctypes.POINTER(P)]
     L.leapfrog_trajectory.argtypes = [P, U64, D, ctypes.POINTER(I32)]
     L.hamiltonian.argtypes = [P, I32, D]
+    L.leapfrog_trajectory_async.argtypes = [P, U64, P, P]
+    L.gibbs_sweep_async.argtypes = [P, U64, P]
+    L.hmc_sweep_record_doubles.argtypes = [P]
+    L.hmc_sweep_record_doubles.restype = ctypes.c_size_t
     L.shell_power.argtypes = [P, I32, D, ctypes.POINTER(ctypes.c_int64)]
     L.gibbs_sweep.argtypes = [P, U64, ctypes.POINTER(HmcSweepStats)]
     L.hmc_set_state.argtypes = [P, I32, P]
@@ -105,6 +110,7 @@ def lib(path=LIB_PATH):
     L.cnn_destroy.restype = None
     for name in EXPORTS:
         if name not in ("hmc_workspace_bytes", "hmc_last_error", "hmc_destroy", "cnn_param_count",
+                        "hmc_sweep_record_doubles",
                         "cnn_last_error", "cnn_destroy"):
             getattr(L, name).restype = ctypes.c_int32
     _lib = L
@@ -215,6 +221,20 @@ class Sampler:
         acc = (ctypes.c_int32 * k)()
         self._check(self.L.leapfrog_trajectory(self.ctx, int(traj_index), dH, acc))
         return np.array(dH[:]), np.array(acc[:], dtype=bool)
+
+    def trajectory_async(self, traj_index, dH, accepted):
+        """Enqueue a trajectory; dH (float64) and accepted (int32) are device tensors [chains]."""
+        self._check(self.L.leapfrog_trajectory_async(self.ctx, int(traj_index),
+                                                     ctypes.c_void_p(dH.data_ptr()),
+                                                     ctypes.c_void_p(accepted.data_ptr())))
+
+    def sweep_record_size(self):
+        return int(self.L.hmc_sweep_record_doubles(self.ctx))
+
+    def sweep_async(self, sweep_index, stats):
+        """Enqueue a sweep; stats is a float64 device tensor of sweep_record_size() values."""
+        self._check(self.L.gibbs_sweep_async(self.ctx, int(sweep_index),
+                                             ctypes.c_void_p(stats.data_ptr())))
 
     def hamiltonian(self, chain=0):
         out = (ctypes.c_double * 3)()

@@ -1124,6 +1124,40 @@ __global__ void __launch_bounds__(kThreads) k_shell_lut(const ChainDev* __restri
     d.lut[q] = (signed char)shell_q((uint64_t)q, d.n, d.nb);
 }
 
+// results of the last trajectory / sweep into caller device buffers (no host
+// round trip): trajectories write dH and the accept flag per chain; sweeps write
+// per chain the record [dH, accepted, rj_dH, rj_accepted, status, P_m (physical
+// units), b_l, Nbar_l], records back to back in chain order
+__global__ void k_export(const ChainDev* __restrict__ ch, int nch, int sweep, double* rec,
+                         int32_t* acc) {
+  const int i = blockIdx.x;
+  if (i >= nch) return;
+  const ChainDev& d = ch[i];
+  if (!sweep) {
+    if (threadIdx.x == 0) {
+      rec[i] = d.P[kDH];
+      acc[i] = d.P[kAcc] != 0.0 ? 1 : 0;
+    }
+    return;
+  }
+  long long off = 0;
+  for (int j = 0; j < i; ++j) off += 5 + ch[j].nb + 2 * ch[j].nsub;
+  double* r = rec + off;
+  const double f = d.box * d.box * d.box / ((double)d.n * d.n * d.n);
+  if (threadIdx.x == 0) {
+    r[0] = d.P[kDH];
+    r[1] = d.P[kAcc];
+    r[2] = d.P[kRjDH];
+    r[3] = d.P[kRjAcc];
+    r[4] = d.P[kStatus];
+  }
+  for (int m = threadIdx.x; m < d.nb; m += blockDim.x) r[5 + m] = d.P[kLam + m] * f;
+  for (int l = threadIdx.x; l < d.nsub; l += blockDim.x) {
+    r[5 + d.nb + l] = d.P[kBias + l];
+    r[5 + d.nb + d.nsub + l] = d.P[kNbar + l];
+  }
+}
+
 // warm start: drn <- mu + sqrt(v / sigma^2) drn with v = exp(logvar), drn the
 // prior draw F^-1(sqrt(lambda_k) F w) and sigma^2 = (1/N^3) sum_m n_m lambda_m its
 // per-voxel variance
@@ -1806,6 +1840,10 @@ void launch_mass_prep(int phase, const ChainDev* ch, int total_r, const float* l
 void launch_shell_lut(const ChainDev* ch, int n, hipStream_t s) {
   const int q = 3 * (n / 2) * (n / 2) + 1;
   hipLaunchKernelGGL(k_shell_lut, dim3((q + kThreads - 1) / kThreads), dim3(kThreads), 0, s, ch);
+}
+void launch_export(const ChainDev* ch, int nch, int sweep, double* rec, int32_t* acc,
+                   hipStream_t s) {
+  hipLaunchKernelGGL(k_export, dim3(nch), dim3(128), 0, s, ch, nch, sweep, rec, acc);
 }
 void launch_warm_combine(const ChainDev* ch, int total_r, const float* mu, const float* logvar,
                          hipStream_t s) {

@@ -60,6 +60,8 @@ void launch_mass_prep(int phase, const ChainDev* ch, int total_r, const float* l
                       hipStream_t s);
 void launch_zpass(int mode, const ChainDev* ch, int nch, int total, int lds, ZArgs a,
                   const float2* tw, int grid_cap, hipStream_t s, int uniform_n);
+void launch_export(const ChainDev* ch, int nch, int sweep, double* rec, int32_t* acc,
+                   hipStream_t s);
 void launch_shell_lut(const ChainDev* ch, int n, hipStream_t s);
 void launch_warm_combine(const ChainDev* ch, int total_r, const float* mu, const float* logvar,
                          hipStream_t s);

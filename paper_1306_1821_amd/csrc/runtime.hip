@@ -691,6 +691,20 @@ hmc_status leapfrog_trajectory(hmc_ctx* c, uint64_t traj_index, double* dH, int3
   return numeric ? fail(c, HMC_ENUMERIC, "non-finite energy; trajectory rejected") : HMC_OK;
 }
 
+hmc_status leapfrog_trajectory_async(hmc_ctx* c, uint64_t traj_index, double* dH_dev,
+                                     int32_t* accepted_dev) {
+  if (!c || !dH_dev || !accepted_dev) return fail(c, HMC_EINVAL, "bad argument");
+  if (c->mass_mixed)
+    return fail(c, HMC_EUNSUPPORTED, "learned mass set on some chains of the context only");
+  launch_set_draw(c->d_draw, (uint32_t)traj_index, c->stream);
+  c->cur_steps = steps_of(c, traj_index);
+  hmc_status st = c->use_graph ? run_graph(c, &c->g_traj[c->cur_steps], run_trajectory)
+                               : run_trajectory(c);
+  if (st != HMC_OK) return st;
+  launch_export(c->d_all, (int)c->ch.size(), 0, dH_dev, accepted_dev, c->stream);
+  return check_launch(c);
+}
+
 hmc_status hamiltonian(hmc_ctx* c, int32_t chain, double* out) {
   if (!c || !out || chain < 0 || chain >= (int)c->ch.size())
     return fail(c, HMC_EINVAL, "bad argument");
@@ -808,6 +822,25 @@ hmc_status gibbs_sweep(hmc_ctx* c, uint64_t sweep_index, hmc_sweep_stats* out) {
     }
   }
   return bad ? fail(c, HMC_ENUMERIC, "a draw or an energy was not finite") : HMC_OK;
+}
+
+size_t hmc_sweep_record_doubles(const hmc_ctx* c) {
+  if (!c) return 0;
+  size_t n = 0;
+  for (auto& k : c->ch) n += 5 + k.dev.nb + 2 * k.dev.nsub;
+  return n;
+}
+
+hmc_status gibbs_sweep_async(hmc_ctx* c, uint64_t sweep_index, double* stats_dev) {
+  if (!c || !stats_dev) return fail(c, HMC_EINVAL, "bad argument");
+  if (c->mass_mixed)
+    return fail(c, HMC_EUNSUPPORTED, "learned mass set on some chains of the context only");
+  launch_set_draw(c->d_draw, (uint32_t)sweep_index, c->stream);
+  c->cur_steps = steps_of(c, sweep_index);
+  hmc_status st = c->use_graph ? run_graph(c, &c->g_sweep[c->cur_steps], run_sweep) : run_sweep(c);
+  if (st != HMC_OK) return st;
+  launch_export(c->d_all, (int)c->ch.size(), 1, stats_dev, nullptr, c->stream);
+  return check_launch(c);
 }
 
 hmc_status hmc_set_state(hmc_ctx* c, int32_t chain, const float* delta_r_dev) {

@@ -158,3 +158,42 @@ def test_drawn_step_counts_with_graphs():
                 assert x["dH"] == y["dH"] and np.array_equal(x["pk"], y["pk"])
     for x, y in zip(runs[0][1], runs[1][1]):
         assert np.array_equal(x, y)
+
+
+def test_async_calls_equal_synchronous_ones():
+    """Queued trajectories / sweeps writing their results to device buffers give the
+    same results and states as the synchronous calls."""
+    mks = [mock("small16"), mock("cfg1")]
+    specs = [chain_spec(m, eps=0.05, nsteps=8, seed=31, chain_id=i, rj=True)
+             for i, m in enumerate(mks)]
+    a, b = Sampler(specs), Sampler(specs)
+    for s in (a, b):
+        for i, m in enumerate(mks):
+            s.set_state(i, start_state(m)[0])
+    ref_t = [a.trajectory(200 + t) for t in range(3)]
+    ref_s = [a.sweep(t) for t in range(3)]
+    dH = torch.zeros((3, 2), dtype=torch.float64, device="cuda")
+    acc = torch.zeros((3, 2), dtype=torch.int32, device="cuda")
+    rec = torch.zeros((3, b.sweep_record_size()), dtype=torch.float64, device="cuda")
+    for t in range(3):
+        b.trajectory_async(200 + t, dH[t], acc[t])
+    for t in range(3):
+        b.sweep_async(t, rec[t])
+    torch.cuda.synchronize()
+    dH, acc, rec = dH.cpu().numpy(), acc.cpu().numpy(), rec.cpu().numpy()
+    for t in range(3):
+        assert np.array_equal(dH[t], ref_t[t][0]) and np.array_equal(acc[t].astype(bool), ref_t[t][1])
+        off = 0
+        for i, st in enumerate(ref_s[t]):
+            r = rec[t, off:]
+            nb, c = len(st["pk"]), len(st["bias"])
+            assert r[0] == st["dH"] and bool(r[1]) == st["accepted"]
+            assert r[2] == st["rj_dH"] and bool(r[3]) == st["rj_accepted"] and r[4] == 0
+            assert np.array_equal(r[5:5 + nb], st["pk"])
+            assert np.array_equal(r[5 + nb:5 + nb + c], st["bias"])
+            assert np.array_equal(r[5 + nb + c:5 + nb + 2 * c], st["nbar"])
+            off += 5 + nb + 2 * c
+    for i in range(2):
+        assert np.array_equal(a.state(i)["delta_k"], b.state(i)["delta_k"])
+    a.close()
+    b.close()
