@@ -179,7 +179,21 @@ struct Plan<N_, T_, Radices<Rs...>> {
 };
 
 // One Stockham stage.  LDS element idx of this pencil is at lds[idx * es].
-template <int N, int T, int R, int NS, int DIR, bool LAST>
+// LDS exchange ordering: a block barrier, or (WAVE) only a wavefront-scope fence
+// when every pencil lives inside one wavefront (its LDS region is then touched by
+// that wavefront alone, whose lanes run in lockstep)
+template <bool WAVE>
+__device__ __forceinline__ void lds_sync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
+template <int N, int T, int R, int NS, int DIR, bool LAST, bool WAVE = false>
 __device__ __forceinline__ void stage(float2* v, float2* lds, int es, int t, bool active,
                                       const float2* __restrict__ tw) {
   constexpr int E = N / T;
@@ -237,21 +251,21 @@ __device__ __forceinline__ void stage(float2* v, float2* lds, int es, int t, boo
     }
   }
   if constexpr (!LAST) {
-    __syncthreads();
+    lds_sync<WAVE>();
     if (active) {
 #pragma unroll
       for (int e = 0; e < E; ++e) v[e] = lds[(t + T * e) * es];
     }
-    __syncthreads();
+    lds_sync<WAVE>();
   }
 }
 
-template <int N, int T, int DIR, int NS, int R, int... Rest>
+template <int N, int T, int DIR, bool WAVE, int NS, int R, int... Rest>
 __device__ __forceinline__ void stages(float2* v, float2* lds, int es, int t, bool active,
                                        const float2* __restrict__ tw) {
   constexpr bool last = sizeof...(Rest) == 0;
-  stage<N, T, R, NS, DIR, last>(v, lds, es, t, active, tw);
-  if constexpr (!last) stages<N, T, DIR, NS * R, Rest...>(v, lds, es, t, active, tw);
+  stage<N, T, R, NS, DIR, last, WAVE>(v, lds, es, t, active, tw);
+  if constexpr (!last) stages<N, T, DIR, WAVE, NS * R, Rest...>(v, lds, es, t, active, tw);
 }
 
 // Full length-N transform of the pencil held in v (cyclic in and out).
@@ -261,7 +275,13 @@ __device__ __forceinline__ void stages(float2* v, float2* lds, int es, int t, bo
 template <int N, int T, int DIR, int... Rs>
 __device__ __forceinline__ void fft(float2* v, float2* lds, int es, int t, bool active,
                                     const float2* __restrict__ tw, Radices<Rs...>) {
-  stages<N, T, DIR, 1, Rs...>(v, lds, es, t, active, tw);
+  stages<N, T, DIR, false, 1, Rs...>(v, lds, es, t, active, tw);
+}
+// the same with wavefront-scope ordering (every pencil inside one wavefront)
+template <int N, int T, int DIR, int... Rs>
+__device__ __forceinline__ void fft_wave(float2* v, float2* lds, int es, int t, bool active,
+                                         const float2* __restrict__ tw, Radices<Rs...>) {
+  stages<N, T, DIR, true, 1, Rs...>(v, lds, es, t, active, tw);
 }
 
 }  // namespace hmcfft

@@ -23,6 +23,9 @@
 #endif
 // non-temporal hints on the state in the k-space pass (HMC_XNT) and on alpha,
 // beta in the real-space pass (HMC_NT)
+#ifndef HMC_ZWAVE
+#define HMC_ZWAVE 1
+#endif
 #ifndef HMC_DOT_F32
 #define HMC_DOT_F32 0
 #endif
@@ -195,6 +198,19 @@ template <int N> constexpr int zrs() {
   }
 }
 template <int N> constexpr int zlds() { return ZC<N>::B * zrs<N>() * 8; }
+// z pass: each row (T threads, T divides 64) lies inside one wavefront and owns its
+// LDS row, so its exchanges need only wavefront-scope ordering (HMC_ZWAVE)
+__device__ __forceinline__ void zsync() { lds_sync<HMC_ZWAVE != 0>(); }
+template <int N, int T, int DIR, class RL>
+__device__ __forceinline__ void zfft(float2* v, float2* lds, int t, bool active,
+                                     const float2* __restrict__ tw) {
+  static_assert(64 % T == 0, "a z-pass row must not straddle wavefronts");
+#if HMC_ZWAVE
+  fft_wave<N, T, DIR>(v, lds, 1, t, active, tw, RL{});
+#else
+  fft<N, T, DIR>(v, lds, 1, t, active, tw, RL{});
+#endif
+}
 
 #define HMC_FOR_N(X) X(8) X(16) X(32) X(64) X(128) X(192) X(256)
 
@@ -655,7 +671,7 @@ __device__ __forceinline__ void zpass(const ChainDev& d, int lt, const ZArgs a, 
 #pragma unroll
     for (int e = 0; e < E; ++e) L[t + T * e] = xr[e];
     if (t == 0) L[M] = xr[E];
-    __syncthreads();
+    zsync();
     // Z_k = (X_k + conj X_{M-k}) + i W_N^-k (X_k - conj X_{M-k}); imaginary parts of
     // the self-conjugate X_0 and X_M are dropped.
 #pragma unroll
@@ -670,8 +686,8 @@ __device__ __forceinline__ void zpass(const ChainDev& d, int lt, const ZArgs a, 
       const float2 r = cmul(cconj(twN[k]), csub(xa, xb));
       v[e] = make_float2(s.x - r.y, s.y + r.x);
     }
-    __syncthreads();
-    fft<M, T, -1>(v, L, 1, t, active, twM, typename C::RL{});
+    zsync();
+    zfft<M, T, -1, typename C::RL>(v, L, t, active, twM);
   } else if constexpr (MODE == Z_R2C) {
 #pragma unroll
     for (int e = 0; e < E; ++e)
@@ -716,12 +732,12 @@ __device__ __forceinline__ void zpass(const ChainDev& d, int lt, const ZArgs a, 
   }
 
   if constexpr (MODE != Z_C2R) {
-    fft<M, T, +1>(v, L, 1, t, active, twM, typename C::RL{});
+    zfft<M, T, +1, typename C::RL>(v, L, t, active, twM);
     if (active) {
 #pragma unroll
       for (int e = 0; e < E; ++e) L[t + T * e] = v[e];
     }
-    __syncthreads();
+    zsync();
     // X_k = E_k + W_N^k O_k, E_k = (Z_k + conj Z_{M-k})/2, O_k = -i (Z_k - conj Z_{M-k})/2
     if (active) {
 #pragma unroll
@@ -741,7 +757,7 @@ __device__ __forceinline__ void zpass(const ChainDev& d, int lt, const ZArgs a, 
     const double s = block_sum(dat, red);
     if (threadIdx.x == 0) d.part[kPartDat * d.maxtiles + lt] = s;
   }
-  __syncthreads();
+  zsync();
 }
 
 template <int MODE>
@@ -804,7 +820,7 @@ __device__ __forceinline__ void row_c2r(const float2* X, float2* L, float2* v, i
 #pragma unroll
   for (int e = 0; e < E; ++e) L[t + T * e] = xr[e];
   if (t == 0) L[M] = xr[E];
-  __syncthreads();
+  zsync();
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int k = t + T * e;
@@ -817,8 +833,8 @@ __device__ __forceinline__ void row_c2r(const float2* X, float2* L, float2* v, i
     const float2 r = cmul(cconj(twN[k]), csub(xa, xb));
     v[e] = make_float2(s.x - r.y, s.y + r.x);
   }
-  __syncthreads();
-  fft<M, T, -1>(v, L, 1, t, active, twM, typename C::RL{});
+  zsync();
+  zfft<M, T, -1, typename C::RL>(v, L, t, active, twM);
 }
 
 // R2C of v (same distribution) into the half-complex row X.
@@ -828,12 +844,12 @@ __device__ __forceinline__ void row_r2c(float2* v, float2* L, float2* X, int t, 
                                         const float2* __restrict__ twM) {
   using C = ZC<N>;
   constexpr int M = N / 2, T = C::T, E = M / T;
-  fft<M, T, +1>(v, L, 1, t, active, twM, typename C::RL{});
+  zfft<M, T, +1, typename C::RL>(v, L, t, active, twM);
   if (active) {
 #pragma unroll
     for (int e = 0; e < E; ++e) L[t + T * e] = v[e];
   }
-  __syncthreads();
+  zsync();
   if (active) {
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -847,7 +863,7 @@ __device__ __forceinline__ void row_r2c(float2* v, float2* L, float2* X, int t, 
     }
     if (t == 0) gst(X + M, make_float2(L[0].x - L[0].y, 0.f));
   }
-  __syncthreads();
+  zsync();
 }
 
 template <int N, int MODE>
@@ -908,7 +924,7 @@ __device__ __forceinline__ void zpass_l(const ChainDev& d, int lt, const ZArgs a
       if (threadIdx.x == 0) d.part[kPartDat * d.maxtiles + lt] = s2;
     }
   }
-  __syncthreads();
+  zsync();
 }
 
 template <int N, int MODE>
