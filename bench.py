@@ -106,22 +106,24 @@ def batched_main(args):
     from paper_1306_1821_amd.binding import Sampler
     from synth import CONFIGS, make_mock
 
-    specs, owner, vox = [], [], 0
-    for name, count in BATCH_GROUPS:
+    # one survey (own mask seed) per grid size; the chains of a size sample its
+    # posterior independently (own chain ids), so R-hat across them is meaningful
+    specs, owner, vox, mocks = [], [], 0, {}
+    for gi, (name, count) in enumerate(BATCH_GROUPS):
+        cfg = dataclasses.replace(CONFIGS[name], seed=100 + gi, mask_seed=gi)
+        mk = mocks[name] = make_mock(cfg, dtype=np.float32)
         for j in range(count):
-            cfg = dataclasses.replace(CONFIGS[name], seed=100 + len(specs), mask_seed=len(specs))
-            mk = make_mock(cfg, dtype=np.float32)
             specs.append(dict(n=cfg.n, box=cfg.box, nb=cfg.nb, R=mk["R"], counts=mk["counts"],
                               bias=mk["bias"], nbar=mk["nbar"], pk=mk["pk_init"],
                               fixed_mask=cfg.fixed_mask, nsteps=cfg.nsteps, eps=args.eps_batch,
-                              rj=True, seed=2013, chain_id=len(specs), delta0=mk["delta"]))
+                              rj=True, seed=2013, chain_id=len(specs)))
             owner.append(name)
             vox += cfg.n ** 3
     print(f"[bench] cfg4: {len(specs)} chains, {vox / 1e6:.1f} M voxels", file=sys.stderr,
           flush=True)
     s = Sampler(specs)
-    for i, sp in enumerate(specs):
-        s.set_state(i, sp["delta0"])
+    for i, name in enumerate(owner):
+        s.set_state(i, mocks[name]["delta"])     # the truth: a posterior draw
     sweep = 0
     for _ in range(args.warmup):
         s.sweep(sweep)
@@ -142,10 +144,23 @@ def batched_main(args):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     nsteps = specs[0]["nsteps"]
+    # convergence across same-size chains: continue (untimed) to --rhat-sweeps sweeps
+    for _ in range(max(0, args.rhat_sweeps - args.steps)):
+        for i, o in enumerate(s.sweep(sweep)):
+            traces[i].append(np.log(o["pk"]))
+        sweep += 1
+    from paper_1306_1821_amd.learned import data_dominated_shells
     rhat = {}
     for name, count in BATCH_GROUPS:
         t = np.array([traces[i] for i, o in enumerate(owner) if o == name])
-        rhat[name] = float(max(diagnostics.split_rhat(t[:, :, m]) for m in range(t.shape[2])))
+        t = t[:, t.shape[1] // 5:]                  # first fifth dropped
+        dd = data_dominated_shells(mocks[name])
+        rhat[name] = {"all_shells_max": float(max(diagnostics.split_rhat(t[:, :, m])
+                                                  for m in range(t.shape[2]))),
+                      "data_dominated_max": float(max(diagnostics.split_rhat(t[:, :, m])
+                                                      for m in dd)),
+                      "data_dominated_shells": int(len(dd)), "chains": count,
+                      "sweeps": int(t.shape[1])}
     s.close()
     value = len(specs) * args.steps * nsteps / dt
     out = {
@@ -155,13 +170,13 @@ def batched_main(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "cfg4: 16 independent chains advancing together, "
                                "8 at 64^3 (2 subsamples), 6 at 128^3 (4), 2 at 192^3 (3), one "
-                               "mask seed per chain, 30 leapfrog steps, joint move on; one "
-                               "step = one sweep of every chain", "eps": args.eps_batch},
+                               "survey (own mask seed) per size, 30 leapfrog steps, joint move "
+                               "on; one step = one sweep of every chain", "eps": args.eps_batch},
         "voxels": vox,
         "equivalent_256_steps_per_s": value / len(specs) * vox / 256 ** 3,
         "launch_grids": chosen,
         "acceptance": float(np.mean(acc)),
-        "split_rhat_lnP_max": rhat,
+        "split_rhat_lnP": rhat,
     }
     print(json.dumps(out), flush=True)
 
@@ -233,6 +248,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--eps-batch", type=float, default=0.03)
+    ap.add_argument("--rhat-sweeps", type=int, default=0,
+                    help="cfg4: total sweeps (timed + untimed) for the R-hat across chains")
     ap.add_argument("--learned", action="store_true",
                     help="learned warm start / mass comparison (steps = measured sweeps per mass)")
     ap.add_argument("--mocks", type=int, default=64)
