@@ -204,6 +204,17 @@ def learned_main(args):
     x = learned.survey_inputs(net, s, 0, mk)
     s.close()
     mu, lv = net.forward(x)
+    # the network's dominant kernels (16-channel implicit-GEMM convolutions on MFMA):
+    # forward over the 256^3 grid, timed with events on the network's stream
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(5):
+        net.forward(x)
+    ev1.record()
+    torch.cuda.synchronize()
+    fwd_ms = ev0.elapsed_time(ev1) / 5
+    n3 = mk["cfg"].n ** 3
+    fwd_flop = 2.0 * 27 * (3 * 16 + 16 * 16 + 16 * 16 + 16 * 2) * n3
     burn = learned.burn_in_study(mk, mu, lv, sweeps=args.burn_sweeps, eps=(args.eps, args.eps),
                                  log=log)
     ess = learned.ess_study(mk, mu, lv, chains=4, burn=100, sweeps=args.steps, eps0=args.eps,
@@ -229,6 +240,10 @@ def learned_main(args):
                         ms_per_sweep=le["ms_per_sweep"],
                         data_dominated=learned.ess_table(le, learned.data_dominated_shells(mk))),
         "ratio_median_ess_per_s": value / float(np.median(pl["ess_per_s"])),
+        "roofline": {"bound": "mfma", "achieved": fwd_flop / (fwd_ms * 1e-3) / 1e12, "peak": 2500.0,
+                     "unit": "TFLOP/s", "frac": fwd_flop / (fwd_ms * 1e-3) / 1e12 / 2500.0,
+                     "traffic": None, "kernel": "CNN forward at 256^3 (k_conv_lds, bf16 MFMA)",
+                     "avg_ms": fwd_ms, "flop_per_launch": fwd_flop},
         "burn_in_sweeps": {k: {"potential": int(r["burn_pot"]), "ln_P": int(r["burn_logbias"])}
                            for k, r in burn.items()},
         "training": {"draws": int(len(own)), "steps": args.train_steps,

@@ -14,6 +14,7 @@
 // B = output gradient), one partial per wave, summed in a fixed order.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -76,10 +77,14 @@ __global__ void __launch_bounds__(256) k_features(long long nv, const float* __r
 
 enum ConvMode : int { C_FWD_GELU = 0, C_FWD_LAST = 1, C_DGRAD = 2 };
 
-// One wave per 16-voxel tile; CS = channel stride of the input (4 or 16).
-template <int CS, int MODE>
+// One wave per 16-voxel tile; CS = channel stride of the input (4 or 16),
+// NC = K chunks (7 for the 3-channel input: 4 taps x 4 channels per chunk; 27
+// otherwise).  The chunk loop is unrolled so that every gather of a tile is
+// issued before the first MFMA needs it.  STORE_Z: keep the pre-activation for
+// the backward pass (inference skips it).
+template <int CS, int MODE, int NC, bool STORE_Z>
 __global__ void __launch_bounds__(256) k_conv(int n, const uint16_t* __restrict__ in,
-                                              const bf16x4* __restrict__ wp, int nchunk,
+                                              const bf16x4* __restrict__ wp,
                                               const float* __restrict__ bias,
                                               const float* __restrict__ zprev,
                                               float* __restrict__ zout,
@@ -91,31 +96,100 @@ __global__ void __launch_bounds__(256) k_conv(int n, const uint16_t* __restrict_
   const int m = lane & 15, grp = lane >> 4;
   const long long v = tile * 16 + m;
   const int x = (int)(v / ((long long)n * n)), y = (int)((v / n) % n), z = (int)(v % n);
-  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-  for (int c = 0; c < nchunk; ++c) {
+  bf16x4 a[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
     const int tap = CS == 16 ? c : 4 * c + grp;
     const int ch0 = CS == 16 ? 4 * grp : 0;
-    bf16x4 a = {0, 0, 0, 0};
+    a[c] = bf16x4{0, 0, 0, 0};
     if (tap < 27) {
       const int xx = x + tap / 9 - 1, yy = y + (tap / 3) % 3 - 1, zz = z + tap % 3 - 1;
       if ((unsigned)xx < (unsigned)n && (unsigned)yy < (unsigned)n && (unsigned)zz < (unsigned)n)
-        a = *reinterpret_cast<const bf16x4*>(in + (((long long)xx * n + yy) * n + zz) * CS + ch0);
+        a[c] = *reinterpret_cast<const bf16x4*>(in + (((long long)xx * n + yy) * n + zz) * CS + ch0);
     }
-    const bf16x4 b = wp[c * 64 + lane];
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
   }
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[c], wp[c * 64 + lane], acc, 0, 0, 0);
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const long long vo = tile * 16 + 4 * grp + i;
     float val = acc[i];
     if (MODE == C_FWD_GELU) {
       val += bias[m];
-      zout[vo * 16 + m] = val;
+      if (STORE_Z) zout[vo * 16 + m] = val;
       aout[vo * 16 + m] = f2bf(gelu(val));
     } else if (MODE == C_FWD_LAST) {
       zout[vo * 16 + m] = val + bias[m];
     } else {
       aout[vo * 16 + m] = f2bf(val * gelu_grad(zprev[vo * 16 + m]));
+    }
+  }
+}
+
+// 16-channel layers with the input brick staged in LDS: a block computes a
+// brick of BX x BY x 16 voxels (x, y, z), loading it once with a one-voxel halo;
+// each of its 4 waves takes BX * BY / 4 rows of 16 z-voxels (one MFMA tile each)
+// and reads the 27 shifted A fragments from LDS.  Needs n a multiple of 16.
+constexpr int kBX = 2, kBY = 8, kBZ = 16;
+constexpr int kHX = kBX + 2, kHY = kBY + 2, kHZ = kBZ + 2;
+constexpr int kHalo = kHX * kHY * kHZ;  // voxels of the haloed brick
+template <int MODE, bool STORE_Z>
+__global__ void __launch_bounds__(256) k_conv_lds(int n, const uint16_t* __restrict__ in,
+                                                  const bf16x4* __restrict__ wp,
+                                                  const float* __restrict__ bias,
+                                                  const float* __restrict__ zprev,
+                                                  float* __restrict__ zout,
+                                                  uint16_t* __restrict__ aout) {
+  __shared__ uint4 brick[kHalo * 2];  // [voxel][2 x 8 bf16 channels]
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nbz = n / kBZ, nby = n / kBY;
+  const int bz = blockIdx.x % nbz, by = (blockIdx.x / nbz) % nby, bx = blockIdx.x / (nbz * nby);
+  const int x0 = bx * kBX, y0 = by * kBY, z0 = bz * kBZ;
+  // stage the brick with its halo (zeros outside the grid)
+  for (int i = threadIdx.x; i < kHalo * 2; i += 256) {
+    const int vox = i >> 1, half = i & 1;
+    const int hz = vox % kHZ, hy = (vox / kHZ) % kHY, hx = vox / (kHZ * kHY);
+    const int xx = x0 + hx - 1, yy = y0 + hy - 1, zz = z0 + hz - 1;
+    uint4 val = make_uint4(0u, 0u, 0u, 0u);
+    if ((unsigned)xx < (unsigned)n && (unsigned)yy < (unsigned)n && (unsigned)zz < (unsigned)n)
+      val = reinterpret_cast<const uint4*>(in + (((long long)xx * n + yy) * n + zz) * 16)[half];
+    brick[i] = val;
+  }
+  bf16x4 w[27];
+#pragma unroll
+  for (int c = 0; c < 27; ++c) w[c] = wp[c * 64 + lane];
+  __syncthreads();
+  const int m = lane & 15, grp = lane >> 4;
+  const uint16_t* lb = reinterpret_cast<const uint16_t*>(brick);
+  constexpr int kRows = kBX * kBY / 4;
+#pragma unroll
+  for (int r = 0; r < kRows; ++r) {
+    const int row = wave * kRows + r;  // (x, y) row of the brick
+    const int rx = row / kBY, ry = row % kBY;
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int c = 0; c < 27; ++c) {
+      const int hx = rx + c / 9, hy = ry + (c / 3) % 3, hz = m + c % 3;
+      const bf16x4 a =
+          *reinterpret_cast<const bf16x4*>(lb + ((hx * kHY + hy) * kHZ + hz) * 16 + 4 * grp);
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, w[c], acc, 0, 0, 0);
+    }
+    const long long vrow = ((long long)(x0 + rx) * n + (y0 + ry)) * n + z0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const long long vo = vrow + 4 * grp + i;
+      float val = acc[i];
+      if (MODE == C_FWD_GELU) {
+        val += bias[m];
+        if (STORE_Z) zout[vo * 16 + m] = val;
+        aout[vo * 16 + m] = f2bf(gelu(val));
+      } else if (MODE == C_FWD_LAST) {
+        zout[vo * 16 + m] = val + bias[m];
+      } else {
+        aout[vo * 16 + m] = f2bf(val * gelu_grad(zprev[vo * 16 + m]));
+      }
     }
   }
 }
@@ -194,6 +268,87 @@ __global__ void __launch_bounds__(256) k_wgrad(int n, const uint16_t* __restrict
       acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, b, acc[t], 0, 0, 0);
     }
   }
+  float* o = part + (size_t)gw * 27 * 256;
+#pragma unroll
+  for (int t = 0; t < 27; ++t)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) o[(t * 16 + 4 * grp + i) * 16 + m] = acc[t][i];
+  db += __shfl_xor(db, 16);
+  db += __shfl_xor(db, 32);
+  if (lane < 16) dbpart[gw * 16 + lane] = db;
+}
+
+// Weight gradient with bricks staged in LDS, channel-major: the block walks
+// bricks of BX x BY x 16 voxels; per brick it stages the haloed activations
+// a[ci][voxel] and the output gradient dz[co][voxel], and each wave runs four
+// K-steps (one 16-voxel z-row each) for all 27 taps, accumulating one partial
+// per wave (A = shifted activations, rows ci; B = dz, columns co).
+template <int CS>
+__global__ void __launch_bounds__(256) k_wgrad_lds(int n, const uint16_t* __restrict__ a,
+                                                   const uint16_t* __restrict__ dz,
+                                                   float* __restrict__ part,
+                                                   float* __restrict__ dbpart) {
+  constexpr int kBV = kBX * kBY * kBZ;
+  static_assert(kBV == 256 && kBX * kBY == 16, "one brick voxel per thread, four rows per wave");
+  __shared__ uint16_t sa[CS][kHalo];
+  __shared__ uint16_t sd[16][kBV];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int m = lane & 15, grp = lane >> 4;
+  const int nbz = n / kBZ, nby = n / kBY;
+  const int nbricks = (n / kBX) * nby * nbz;
+  f32x4 acc[27];
+#pragma unroll
+  for (int t = 0; t < 27; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float db = 0.f;
+  for (int brick = blockIdx.x; brick < nbricks; brick += gridDim.x) {
+    const int bz = brick % nbz, by = (brick / nbz) % nby, bx = brick / (nbz * nby);
+    const int x0 = bx * kBX, y0 = by * kBY, z0 = bz * kBZ;
+    __syncthreads();  // the previous brick's reads are done
+    for (int vox = threadIdx.x; vox < kHalo; vox += 256) {
+      const int hz = vox % kHZ, hy = (vox / kHZ) % kHY, hx = vox / (kHZ * kHY);
+      const int xx = x0 + hx - 1, yy = y0 + hy - 1, zz = z0 + hz - 1;
+      if ((unsigned)xx < (unsigned)n && (unsigned)yy < (unsigned)n && (unsigned)zz < (unsigned)n) {
+        const uint16_t* src = a + (((long long)xx * n + yy) * n + zz) * CS;
+#pragma unroll
+        for (int ch = 0; ch < CS; ++ch) sa[ch][vox] = src[ch];
+      } else {
+#pragma unroll
+        for (int ch = 0; ch < CS; ++ch) sa[ch][vox] = 0;
+      }
+    }
+    {
+      const int v = threadIdx.x;  // kBV == 256 voxels of the brick, one per thread
+      const int vz = v % kBZ, vy = (v / kBZ) % kBY, vx = v / (kBZ * kBY);
+      const uint4* src = reinterpret_cast<const uint4*>(
+          dz + (((long long)(x0 + vx) * n + (y0 + vy)) * n + (z0 + vz)) * 16);
+      const uint4 lo = src[0], hi = src[1];
+      const uint32_t wds[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+#pragma unroll
+      for (int ch = 0; ch < 16; ++ch)
+        sd[ch][v] = (uint16_t)(ch & 1 ? wds[ch >> 1] >> 16 : wds[ch >> 1] & 0xffffu);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const int row = wave * 4 + ks;  // (x, y) row of the brick, 16 voxels along z
+      const int rx = row / kBY, ry = row % kBY;
+      const bf16x4 b = *reinterpret_cast<const bf16x4*>(&sd[m][row * kBZ + 4 * grp]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) db += bf2f((uint16_t)b[i]);
+#pragma unroll
+      for (int t = 0; t < 27; ++t) {
+        const int hx = rx + t / 9, hy = ry + (t / 3) % 3, hz0 = 4 * grp + t % 3;
+        bf16x4 av = {0, 0, 0, 0};
+        if (m < CS) {
+          const uint16_t* p = &sa[m < CS ? m : 0][(hx * kHY + hy) * kHZ + hz0];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) av[i] = (short)p[i];
+        }
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, b, acc[t], 0, 0, 0);
+      }
+    }
+  }
+  const int gw = blockIdx.x * 4 + wave;
   float* o = part + (size_t)gw * 27 * 256;
 #pragma unroll
   for (int t = 0; t < 27; ++t)
@@ -338,21 +493,38 @@ hmc_status ensure(cnn_ctx* c, int n) {
   return HMC_OK;
 }
 
-hmc_status forward(cnn_ctx* c, int n, const float* in3) {
+template <bool STORE_Z>
+hmc_status forward_t(cnn_ctx* c, int n, const float* in3) {
   const long long nv = (long long)n * n * n;
   const int blocks = (int)((nv / 16 + 3) / 4);
   hipLaunchKernelGGL(k_input, dim3(4096), dim3(256), 0, c->stream, nv, in3, c->a0);
-  hipLaunchKernelGGL((k_conv<4, C_FWD_GELU>), dim3(blocks), dim3(256), 0, c->stream, n, c->a0,
-                     c->wp[0], 7, c->p + off_b(0), nullptr, c->z[0], c->a[0]);
-  for (int l = 1; l < 3; ++l)
-    hipLaunchKernelGGL((k_conv<16, C_FWD_GELU>), dim3(blocks), dim3(256), 0, c->stream, n,
-                       c->a[l - 1], c->wp[l], 27, c->p + off_b(l), nullptr, c->z[l], c->a[l]);
+  hipLaunchKernelGGL((k_conv<4, C_FWD_GELU, 7, STORE_Z>), dim3(blocks), dim3(256), 0, c->stream,
+                     n, c->a0, c->wp[0], c->p + off_b(0), nullptr, c->z[0], c->a[0]);
+  const bool lds = n % kBZ == 0;
+  const int lblocks = lds ? (n / kBX) * (n / kBY) * (n / kBZ) : 0;
+  for (int l = 1; l < 3; ++l) {
+    if (lds)
+      hipLaunchKernelGGL((k_conv_lds<C_FWD_GELU, STORE_Z>), dim3(lblocks), dim3(256), 0,
+                         c->stream, n, c->a[l - 1], c->wp[l], c->p + off_b(l), nullptr, c->z[l],
+                         c->a[l]);
+    else
+      hipLaunchKernelGGL((k_conv<16, C_FWD_GELU, 27, STORE_Z>), dim3(blocks), dim3(256), 0,
+                         c->stream, n, c->a[l - 1], c->wp[l], c->p + off_b(l), nullptr, c->z[l],
+                         c->a[l]);
+  }
   // last layer: bias padded to 16 channels through a small device copy
-  hipLaunchKernelGGL((k_conv<16, C_FWD_LAST>), dim3(blocks), dim3(256), 0, c->stream, n, c->a[2],
-                     c->wp[3], 27, c->g + n_params(), nullptr, c->z[3], nullptr);
+  if (lds)
+    hipLaunchKernelGGL((k_conv_lds<C_FWD_LAST, true>), dim3(lblocks), dim3(256), 0, c->stream, n,
+                       c->a[2], c->wp[3], c->g + n_params(), nullptr, c->z[3], nullptr);
+  else
+    hipLaunchKernelGGL((k_conv<16, C_FWD_LAST, 27, true>), dim3(blocks), dim3(256), 0, c->stream,
+                       n, c->a[2], c->wp[3], c->g + n_params(), nullptr, c->z[3], nullptr);
   CCHK(c, hipGetLastError());
   return HMC_OK;
 }
+// forward for training (keeps the pre-activations) and for inference
+hmc_status forward(cnn_ctx* c, int n, const float* in3) { return forward_t<true>(c, n, in3); }
+hmc_status infer(cnn_ctx* c, int n, const float* in3) { return forward_t<false>(c, n, in3); }
 
 hmc_status gradient(cnn_ctx* c, int n, const float* in3, const float* target, double* loss) {
   hmc_status st = forward(c, n, in3);
@@ -362,14 +534,23 @@ hmc_status gradient(cnn_ctx* c, int n, const float* in3, const float* target, do
   hipLaunchKernelGGL(k_loss, dim3(1024), dim3(256), 0, c->stream, nv, c->z[3], target, c->dzA,
                      c->lpart);
   const long long nchunks = nv / 16;
+  const bool lds = n % kBZ == 0;
+  const int nbricks = lds ? (n / kBX) * (n / kBY) * (n / kBZ) : 0;
   const int cpw = (int)((nchunks + kWaves - 1) / kWaves);
-  const int nw = (int)((nchunks + cpw - 1) / cpw);
+  const int gblocks = lds ? std::min(nbricks, kWaves / 4) : 0;
+  const int nw = lds ? 4 * gblocks : (int)((nchunks + cpw - 1) / cpw);
   const int wblocks = (nw + 3) / 4;
   uint16_t* dz = c->dzA;
   uint16_t* other = c->dzB;
   for (int l = 3; l >= 0; --l) {
     const uint16_t* ain = l == 0 ? c->a0 : c->a[l - 1];
-    if (l == 0)
+    if (lds && l == 0)
+      hipLaunchKernelGGL(k_wgrad_lds<4>, dim3(gblocks), dim3(256), 0, c->stream, n, ain, dz,
+                         c->wpart, c->dbpart);
+    else if (lds)
+      hipLaunchKernelGGL(k_wgrad_lds<16>, dim3(gblocks), dim3(256), 0, c->stream, n, ain, dz,
+                         c->wpart, c->dbpart);
+    else if (l == 0)
       hipLaunchKernelGGL(k_wgrad<4>, dim3(wblocks), dim3(256), 0, c->stream, n, ain, dz, cpw,
                          c->wpart, c->dbpart);
     else
@@ -379,8 +560,13 @@ hmc_status gradient(cnn_ctx* c, int n, const float* in3, const float* target, do
     hipLaunchKernelGGL(k_wreduce, dim3((tot + 255) / 256), dim3(256), 0, c->stream, c->wpart,
                        c->dbpart, nw, kCin[l], kCout[l], c->g + off_w(l), c->g + off_b(l));
     if (l > 0) {
-      hipLaunchKernelGGL((k_conv<16, C_DGRAD>), dim3(blocks), dim3(256), 0, c->stream, n, dz,
-                         c->wd[l], 27, nullptr, c->z[l - 1], nullptr, other);
+      if (n % kBZ == 0)
+        hipLaunchKernelGGL((k_conv_lds<C_DGRAD, true>), dim3((n / kBX) * (n / kBY) * (n / kBZ)),
+                           dim3(256), 0, c->stream, n, dz, c->wd[l], nullptr, c->z[l - 1],
+                           nullptr, other);
+      else
+        hipLaunchKernelGGL((k_conv<16, C_DGRAD, 27, true>), dim3(blocks), dim3(256), 0,
+                           c->stream, n, dz, c->wd[l], nullptr, c->z[l - 1], nullptr, other);
       std::swap(dz, other);
     }
   }
@@ -480,7 +666,7 @@ hmc_status cnn_forward(cnn_ctx* c, int32_t n, const float* in3, float* mu, float
   if (!c || !in3) return cfail(c, HMC_EINVAL, "null argument");
   hmc_status st = ensure(c, n);
   if (st != HMC_OK) return st;
-  if ((st = forward(c, n, in3)) != HMC_OK) return st;
+  if ((st = infer(c, n, in3)) != HMC_OK) return st;
   const long long nv = (long long)n * n * n;
   hipLaunchKernelGGL(k_outputs, dim3(4096), dim3(256), 0, c->stream, nv, c->z[3], mu, logvar);
   CCHK(c, hipGetLastError());
