@@ -298,7 +298,7 @@ def main():
         s.sweep(sweep)
         sweep += 1
     torch.cuda.synchronize()
-    s.timing(1)
+    s.timing(0x11)                      # HIP events around the k-space step passes only
     acc, rj_acc = [], []
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -319,6 +319,11 @@ def main():
         s.trajectory(10_000 + i)
     torch.cuda.synchronize()
     dt_traj = time.perf_counter() - t1
+    # per-pass breakdown (events around every pass) on a few more trajectories
+    s.timing(1)
+    for i in range(3):
+        s.trajectory(20_000 + i)
+    ms_all, launches_all = s.timing(0)
 
     steps = args.steps * spec["nsteps"]
     value = steps / dt
@@ -350,9 +355,9 @@ def main():
         "acceptance": float(np.mean(acc)),
         "rj_acceptance": float(np.mean(rj_acc)),
         "trajectory_leapfrog_steps_per_s": ntraj * spec["nsteps"] / dt_traj,
-        "pass_ms_per_step": {"kspace": avg_ms,
-                             "ypass": ms[1] / max(1, launches[1]),
-                             "zpass": ms[2] / max(1, launches[2])},
+        "pass_ms_per_step": {"kspace": ms_all[0] / max(1, launches_all[0]),
+                             "ypass": ms_all[1] / max(1, launches_all[1]),
+                             "zpass": ms_all[2] / max(1, launches_all[2])},
     }
     s.close()
     del s

@@ -120,6 +120,7 @@ struct hmc_ctx {
   bool mass_mixed = false;   // some chains only have a learned mass: no trajectories
   // pass timing (hmc_timing)
   bool timing = false;
+  int timing_mask = 0xf;  // pass classes that record events
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_used;
   double t_ms[4] = {0, 0, 0, 0};
@@ -175,7 +176,7 @@ struct Timed {
   int kind;
   hipEvent_t a = nullptr, b = nullptr;
   Timed(hmc_ctx* c_, int kind_, hipStream_t s) : c(c_), kind(kind_) {
-    if (!c->timing) return;
+    if (!c->timing || !(c->timing_mask & (1 << kind))) return;
     a = ev_get(c);
     b = ev_get(c);
     if (a) (void)hipEventRecord(a, s);
@@ -1067,12 +1068,13 @@ hmc_status hmc_timing(hmc_ctx* c, int32_t enable, double* ms, int64_t* launches)
     if (ms) ms[i] = c->t_ms[i];
     if (launches) launches[i] = c->t_n[i];
   }
-  if (enable == 1) {
+  if (enable == 1 || (enable & ~0xf) == 0x10) {
     for (int i = 0; i < 4; ++i) {
       c->t_ms[i] = 0.0;
       c->t_n[i] = 0;
     }
     c->timing = true;
+    c->timing_mask = enable == 1 ? 0xf : (enable & 0xf);
   } else if (enable == 0) {
     c->timing = false;
   }
