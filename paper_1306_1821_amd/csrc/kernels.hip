@@ -445,11 +445,16 @@ __device__ __forceinline__ void xpass(const ChainDev& d, int lt, const XArgs a, 
                                                 : d.gk;
         gsti(out, offs(e), g);
       }
-      if (dot && active && me >= 0) {
-        const float2 x = gldi(dkb, offs(e));
-        const float s = (a.flags & XF_SCALE) ? tf[kTScale + me] : 1.f;
-        const double val = wz * ((double)(s * x.x) * g.x + (double)(s * x.y) * g.y);
-        atomicAdd(&bins[(threadIdx.x >> 6) * kMaxBins + me], (bin_t)val);
+      if (dot) {
+        double val = 0.0;
+        int mm = -1;
+        if (active && me >= 0) {
+          const float2 x = gldi(dkb, offs(e));
+          const float s = (a.flags & XF_SCALE) ? tf[kTScale + me] : 1.f;
+          val = wz * ((double)(s * x.x) * g.x + (double)(s * x.y) * g.y);
+          mm = me;
+        }
+        if (mm >= 0) atomicAdd(&bins[(threadIdx.x >> 6) * kMaxBins + mm], (bin_t)val);
       }
     }
   } else {
