@@ -193,7 +193,19 @@ __device__ __forceinline__ void lds_sync() {
   }
 }
 
-template <int N, int T, int R, int NS, int DIR, bool LAST, bool WAVE = false>
+// PAD > 0 inserts one unused slot after every 2^PAD elements of the pencil
+// (element i at lds[i * es + (i >> PAD)]): it spreads the stride-R writes of a
+// stage over the LDS banks when a pencil is contiguous (es = 1).
+template <int PAD>
+__device__ __forceinline__ int lds_at(int i, int es) {
+  if constexpr (PAD > 0) {
+    return i * es + (i >> PAD);
+  } else {
+    return i * es;
+  }
+}
+
+template <int N, int T, int R, int NS, int DIR, bool LAST, bool WAVE = false, int PAD = 0>
 __device__ __forceinline__ void stage(float2* v, float2* lds, int es, int t, bool active,
                                       const float2* __restrict__ tw) {
   constexpr int E = N / T;
@@ -246,7 +258,7 @@ __device__ __forceinline__ void stage(float2* v, float2* lds, int es, int t, boo
     } else {
       if (active) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) lds[((j - k) * R + k + r * NS) * es] = a[r];
+        for (int r = 0; r < R; ++r) lds[lds_at<PAD>((j - k) * R + k + r * NS, es)] = a[r];
       }
     }
   }
@@ -254,18 +266,18 @@ __device__ __forceinline__ void stage(float2* v, float2* lds, int es, int t, boo
     lds_sync<WAVE>();
     if (active) {
 #pragma unroll
-      for (int e = 0; e < E; ++e) v[e] = lds[(t + T * e) * es];
+      for (int e = 0; e < E; ++e) v[e] = lds[lds_at<PAD>(t + T * e, es)];
     }
     lds_sync<WAVE>();
   }
 }
 
-template <int N, int T, int DIR, bool WAVE, int NS, int R, int... Rest>
+template <int N, int T, int DIR, bool WAVE, int PAD, int NS, int R, int... Rest>
 __device__ __forceinline__ void stages(float2* v, float2* lds, int es, int t, bool active,
                                        const float2* __restrict__ tw) {
   constexpr bool last = sizeof...(Rest) == 0;
-  stage<N, T, R, NS, DIR, last, WAVE>(v, lds, es, t, active, tw);
-  if constexpr (!last) stages<N, T, DIR, WAVE, NS * R, Rest...>(v, lds, es, t, active, tw);
+  stage<N, T, R, NS, DIR, last, WAVE, PAD>(v, lds, es, t, active, tw);
+  if constexpr (!last) stages<N, T, DIR, WAVE, PAD, NS * R, Rest...>(v, lds, es, t, active, tw);
 }
 
 // Full length-N transform of the pencil held in v (cyclic in and out).
@@ -275,13 +287,14 @@ __device__ __forceinline__ void stages(float2* v, float2* lds, int es, int t, bo
 template <int N, int T, int DIR, int... Rs>
 __device__ __forceinline__ void fft(float2* v, float2* lds, int es, int t, bool active,
                                     const float2* __restrict__ tw, Radices<Rs...>) {
-  stages<N, T, DIR, false, 1, Rs...>(v, lds, es, t, active, tw);
+  stages<N, T, DIR, false, 0, 1, Rs...>(v, lds, es, t, active, tw);
 }
-// the same with wavefront-scope ordering (every pencil inside one wavefront)
-template <int N, int T, int DIR, int... Rs>
+// the same with wavefront-scope ordering (every pencil inside one wavefront) and
+// an optional padded LDS layout (lds_at)
+template <int N, int T, int DIR, int PAD = 0, int... Rs>
 __device__ __forceinline__ void fft_wave(float2* v, float2* lds, int es, int t, bool active,
                                          const float2* __restrict__ tw, Radices<Rs...>) {
-  stages<N, T, DIR, true, 1, Rs...>(v, lds, es, t, active, tw);
+  stages<N, T, DIR, true, PAD, 1, Rs...>(v, lds, es, t, active, tw);
 }
 
 }  // namespace hmcfft

@@ -56,6 +56,27 @@
 #ifndef HMC_XCD
 #define HMC_XCD 1
 #endif
+// minimum resident waves per SIMD asked of the compiler for the single-size
+// real-space force pass (HMC_ZOCC), the k-space forward pass (HMC_XFOCC) and
+// the k-space step pass (HMC_XSOCC); 1 leaves register allocation free
+// z pass: padded LDS rows for the transform exchanges (HMC_ZLPAD) and the
+// real-transform partner exchange X_k <-> X_{M-k} by DPP lane moves inside a row
+// of 16 lanes instead of an LDS round trip (HMC_ZDPP, rows of 16 threads)
+#ifndef HMC_ZLPAD
+#define HMC_ZLPAD 1
+#endif
+#ifndef HMC_ZDPP
+#define HMC_ZDPP 1
+#endif
+#ifndef HMC_ZOCC
+#define HMC_ZOCC 1
+#endif
+#ifndef HMC_XFOCC
+#define HMC_XFOCC 1
+#endif
+#ifndef HMC_XSOCC
+#define HMC_XSOCC 1
+#endif
 
 namespace hmc {
 using namespace hmcfft;
@@ -198,6 +219,12 @@ template <int N> constexpr int zrs() {
   }
 }
 template <int N> constexpr int zlds() { return ZC<N>::B * zrs<N>() * 8; }
+static_assert(HMC_ZLPAD == 0 || HMC_ZWAVE != 0, "padded z rows need the wavefront-scope transform");
+#define HMC_ZROW_FITS(NN) static_assert((NN / 2 - 1) + (NN / 2 - 1) / 16 < zrs<NN>(), "padded z row");
+HMC_ZROW_FITS(8) HMC_ZROW_FITS(16) HMC_ZROW_FITS(32) HMC_ZROW_FITS(64) HMC_ZROW_FITS(128)
+HMC_ZROW_FITS(192) HMC_ZROW_FITS(256)
+#undef HMC_ZROW_FITS
+
 // z pass: each row (T threads, T divides 64) lies inside one wavefront and owns its
 // LDS row, so its exchanges need only wavefront-scope ordering (HMC_ZWAVE)
 __device__ __forceinline__ void zsync() { lds_sync<HMC_ZWAVE != 0>(); }
@@ -206,10 +233,106 @@ __device__ __forceinline__ void zfft(float2* v, float2* lds, int t, bool active,
                                      const float2* __restrict__ tw) {
   static_assert(64 % T == 0, "a z-pass row must not straddle wavefronts");
 #if HMC_ZWAVE
-  fft_wave<N, T, DIR>(v, lds, 1, t, active, tw, RL{});
+  fft_wave<N, T, DIR, HMC_ZLPAD ? 4 : 0>(v, lds, 1, t, active, tw, RL{});
 #else
   fft<N, T, DIR>(v, lds, 1, t, active, tw, RL{});
 #endif
+}
+
+// Inside each row of 16 lanes: lane t >= 1 receives `src` of lane 16 - t, lane 0
+// keeps `own` (DPP row_mirror, then row_shr:1, whose lane 0 has no source and keeps
+// the old value).
+__device__ __forceinline__ float dpp_partner16(float own, float src) {
+  const int m = __builtin_amdgcn_update_dpp(0, __float_as_int(src), 0x140, 0xf, 0xf, false);
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(own), m, 0x111, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float2 dpp_partner16(float2 own, float2 src) {
+  return make_float2(dpp_partner16(own.x, src.x), dpp_partner16(own.y, src.y));
+}
+
+// Real transform of length N = 2M through a complex one of length M, row held
+// cyclically by T threads (element k = t + T e).  C2R input step: from the
+// half-complex X (xr[e] = X_{t+Te}, xr[E] = X_M) form
+//   Z_k = (X_k + conj X_{M-k}) + i W_N^-k (X_k - conj X_{M-k}),
+// dropping the imaginary parts of the self-conjugate X_0 and X_M.  X_{M-k} sits
+// in lane T - t as element E-1-e (t >= 1) and in lane 0 itself as element E - e;
+// rows of 16 lanes fetch it by DPP, others through the LDS row L.
+template <int N, int T, int E>
+__device__ __forceinline__ void c2r_pre(const float2* xr, float2* v, float2* L, int t,
+                                        const float2* __restrict__ twN) {
+  constexpr int M = N / 2;
+  if constexpr (HMC_ZDPP && T == 16) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int k = t + T * e;
+      float2 xa = xr[e], xb = cconj(dpp_partner16(xr[E - e], xr[E - 1 - e]));
+      if (k == 0) {
+        xa = make_float2(xr[0].x, 0.f);
+        xb = make_float2(xr[E].x, 0.f);
+      }
+      const float2 s = cadd(xa, xb);
+      const float2 r = cmul(cconj(twN[k]), csub(xa, xb));
+      v[e] = make_float2(s.x - r.y, s.y + r.x);
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e) L[t + T * e] = xr[e];
+    if (t == 0) L[M] = xr[E];
+    zsync();
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int k = t + T * e;
+      float2 xa = L[k], xb = cconj(L[M - k]);
+      if (k == 0) {
+        xa = make_float2(L[0].x, 0.f);
+        xb = make_float2(L[M].x, 0.f);
+      }
+      const float2 s = cadd(xa, xb);
+      const float2 r = cmul(cconj(twN[k]), csub(xa, xb));
+      v[e] = make_float2(s.x - r.y, s.y + r.x);
+    }
+    zsync();
+  }
+}
+
+// R2C output step from Z = the length-M transform held cyclically in v:
+//   X_k = E_k + W_N^k O_k, E_k = (Z_k + conj Z_{M-k})/2, O_k = -i (Z_k - conj Z_{M-k})/2,
+// X_M = Re Z_0 - Im Z_0; st(k, X_k) for k = 0..M (active rows only).  Z_{M-k}: lane
+// T - t, element E-1-e (t >= 1); lane 0, element (E - e) mod E.
+template <int N, int T, int E, class Store>
+__device__ __forceinline__ void r2c_post(const float2* v, float2* L, int t, bool active,
+                                         const float2* __restrict__ twN, Store st) {
+  constexpr int M = N / 2;
+  float2 zcv[E];
+  if constexpr (HMC_ZDPP && T == 16) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) zcv[e] = cconj(dpp_partner16(v[(E - e) % E], v[E - 1 - e]));
+  } else {
+    if (active) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) L[t + T * e] = v[e];
+    }
+    zsync();
+    if (active) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int k = t + T * e;
+        zcv[e] = cconj(L[k == 0 ? 0 : M - k]);
+      }
+    }
+  }
+  if (active) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int k = t + T * e;
+      const float2 zk = v[e], zc = zcv[e];
+      const float2 ev = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y + zc.y));
+      const float2 df = csub(zk, zc);
+      const float2 od = make_float2(0.5f * df.y, -0.5f * df.x);
+      st(k, cadd(ev, cmul(twN[k], od)));
+    }
+    if (t == 0) st(M, make_float2(v[0].x - v[0].y, 0.f));
+  }
 }
 
 #define HMC_FOR_N(X) X(8) X(16) X(32) X(64) X(128) X(192) X(256)
@@ -336,25 +459,48 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return red[0] + red[1] + red[2] + red[3];
 }
 
-// per-wave shell bins in LDS: bins[wave * kMaxBins + m].  HMC_DOT_F32: the
-// k-space pass accumulates its shell dot products in float per wave (flushed to
-// float64 per tile), which halves the LDS atomic traffic.
+// Shell bins of the k-space dot pass in LDS: kBinCopies copies per wave,
+// bins[(wave * kBinCopies + copy) * kBinStride + m].  Lanes of neighbouring
+// columns and neighbouring x frequencies (mostly the same shell) add into
+// different copies, which cuts the same-address serialisation of the LDS atomics;
+// each copy is written by one wave only, in program order, so the per-tile sums
+// (fixed order over waves and copies) are reproducible.  The odd row stride puts
+// the copies of one shell on different banks.  HMC_DOT_F32: float bins (flushed
+// to float64 per tile).
 #if HMC_DOT_F32
 typedef float bin_t;
 #else
 typedef double bin_t;
 #endif
+#ifndef HMC_DOT_COPIES
+#define HMC_DOT_COPIES 2
+#endif
+constexpr int kBinCopies = HMC_DOT_COPIES;
+static_assert(kBinCopies == 1 || kBinCopies == 2 || kBinCopies == 4, "bin copies per wave");
+constexpr int kBinStride = kMaxBins + 1;
+constexpr int kBinSlots = 4 * kBinCopies * kBinStride;
+// copy of a lane: bit 0 = column parity, bit 1 = parity of the pencil's x row
+// within the wave (lane = row B + column for B < 64; the two low column bits for B >= 64)
+template <int B>
+__device__ __forceinline__ int bin_copy() {
+  const int lane = threadIdx.x & 63;
+  constexpr int hb = B >= 64 ? 1 : (B == 32 ? 5 : B == 16 ? 4 : B == 8 ? 3 : B == 4 ? 2 : 1);
+  return ((lane & 1) | (((lane >> hb) & 1) << 1)) & (kBinCopies - 1);
+}
 template <class B>
 __device__ __forceinline__ void bins_zero(B* bins) {
-  for (int i = threadIdx.x; i < 4 * kMaxBins; i += kThreads) bins[i] = (B)0;
+  for (int i = threadIdx.x; i < kBinSlots; i += kThreads) bins[i] = (B)0;
   __syncthreads();
 }
 template <class B>
 __device__ __forceinline__ void bins_flush(B* bins, double* dst, int nb) {
   __syncthreads();
-  for (int m = threadIdx.x; m < nb; m += kThreads)
-    dst[m] = (((double)bins[m] + (double)bins[kMaxBins + m]) + (double)bins[2 * kMaxBins + m]) +
-             (double)bins[3 * kMaxBins + m];
+  for (int m = threadIdx.x; m < nb; m += kThreads) {
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4 * kBinCopies; ++i) s += (double)bins[i * kBinStride + m];
+    dst[m] = s;
+  }
   __syncthreads();
 }
 
@@ -454,7 +600,8 @@ __device__ __forceinline__ void xpass(const ChainDev& d, int lt, const XArgs a, 
           val = wz * ((double)(s * x.x) * g.x + (double)(s * x.y) * g.y);
           mm = me;
         }
-        if (mm >= 0) atomicAdd(&bins[(threadIdx.x >> 6) * kMaxBins + mm], (bin_t)val);
+        if (mm >= 0)
+          atomicAdd(&bins[((threadIdx.x >> 6) * kBinCopies + bin_copy<B>()) * kBinStride + mm], (bin_t)val);
       }
     }
   } else {
@@ -546,7 +693,11 @@ __global__ void __launch_bounds__(kThreads) k_xpass(const ChainDev* __restrict__
                                                      const float2* __restrict__ tw) {
   extern __shared__ float2 lds[];
   __shared__ double red[4];
-  __shared__ bin_t bins[4 * kMaxBins];
+  bin_t* bins = nullptr;
+  if constexpr (MODE == X_FWD) {
+    __shared__ bin_t sbins[kBinSlots];
+    bins = sbins;
+  }
   for (TileWalk w = tile_walk(total); w.cur < w.end; w.cur += w.step) {
     const int tile = w.cur;
     const int c = find_chain(ch, nch, tile, kTileXY);
@@ -561,14 +712,22 @@ __global__ void __launch_bounds__(kThreads) k_xpass(const ChainDev* __restrict__
   }
 }
 
+template <int MODE> struct XOcc {
+  static constexpr int w = MODE == X_FWD ? HMC_XFOCC : MODE == X_STEP ? HMC_XSOCC : 1;
+};
 // single-size variant: every chain of the launch has this N (lower register use)
 template <int N, int MODE>
-__global__ void __launch_bounds__(kThreads) k_xpass_n(const ChainDev* __restrict__ ch, int nch,
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(XOcc<MODE>::w)))
+k_xpass_n(const ChainDev* __restrict__ ch, int nch,
                                                        int total, XArgs a,
                                                        const float2* __restrict__ tw) {
   extern __shared__ float2 lds[];
   __shared__ double red[4];
-  __shared__ bin_t bins[4 * kMaxBins];
+  bin_t* bins = nullptr;
+  if constexpr (MODE == X_FWD) {
+    __shared__ bin_t sbins[kBinSlots];
+    bins = sbins;
+  }
   for (TileWalk w = tile_walk(total); w.cur < w.end; w.cur += w.step) {
     const int tile = w.cur;
     const int c = find_chain(ch, nch, tile, kTileXY);
@@ -673,25 +832,7 @@ __device__ __forceinline__ void zpass(const ChainDev& d, int lt, const ZArgs a, 
 #pragma unroll
     for (int e = 0; e < E; ++e) xr[e] = gldi(Tb, xo + t + T * e);
     xr[E] = gldi(Tb, xo + M);
-#pragma unroll
-    for (int e = 0; e < E; ++e) L[t + T * e] = xr[e];
-    if (t == 0) L[M] = xr[E];
-    zsync();
-    // Z_k = (X_k + conj X_{M-k}) + i W_N^-k (X_k - conj X_{M-k}); imaginary parts of
-    // the self-conjugate X_0 and X_M are dropped.
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int k = t + T * e;
-      float2 xa = L[k], xb = cconj(L[M - k]);
-      if (k == 0) {
-        xa = make_float2(L[0].x, 0.f);
-        xb = make_float2(L[M].x, 0.f);
-      }
-      const float2 s = cadd(xa, xb);
-      const float2 r = cmul(cconj(twN[k]), csub(xa, xb));
-      v[e] = make_float2(s.x - r.y, s.y + r.x);
-    }
-    zsync();
+    c2r_pre<N, T, E>(xr, v, L, t, twN);
     zfft<M, T, -1, typename C::RL>(v, L, t, active, twM);
   } else if constexpr (MODE == Z_R2C) {
 #pragma unroll
@@ -738,25 +879,7 @@ __device__ __forceinline__ void zpass(const ChainDev& d, int lt, const ZArgs a, 
 
   if constexpr (MODE != Z_C2R) {
     zfft<M, T, +1, typename C::RL>(v, L, t, active, twM);
-    if (active) {
-#pragma unroll
-      for (int e = 0; e < E; ++e) L[t + T * e] = v[e];
-    }
-    zsync();
-    // X_k = E_k + W_N^k O_k, E_k = (Z_k + conj Z_{M-k})/2, O_k = -i (Z_k - conj Z_{M-k})/2
-    if (active) {
-#pragma unroll
-      for (int e = 0; e < E; ++e) {
-        const int k = t + T * e;
-        const float2 zk = L[k];
-        const float2 zc = cconj(L[k == 0 ? 0 : M - k]);
-        const float2 ev = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y + zc.y));
-        const float2 df = csub(zk, zc);
-        const float2 od = make_float2(0.5f * df.y, -0.5f * df.x);
-        gsti(Tb, xo + k, cadd(ev, cmul(twN[k], od)));
-      }
-      if (t == 0) gsti(Tb, xo + M, make_float2(L[0].x - L[0].y, 0.f));
-    }
+    r2c_post<N, T, E>(v, L, t, active, twN, [&](int k, float2 x) { gsti(Tb, xo + k, x); });
   }
   if (a.flags & ZF_DATA) {
     const double s = block_sum(dat, red);
@@ -785,8 +908,12 @@ __global__ void __launch_bounds__(kThreads) k_zpass(const ChainDev* __restrict__
   }
 }
 
+template <int MODE> struct ZOcc {
+  static constexpr int w = MODE == Z_GRAD ? HMC_ZOCC : 1;
+};
 template <int N, int MODE>
-__global__ void __launch_bounds__(kThreads) k_zpass_n(const ChainDev* __restrict__ ch, int nch,
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(ZOcc<MODE>::w)))
+k_zpass_n(const ChainDev* __restrict__ ch, int nch,
                                                        int total, ZArgs a,
                                                        const float2* __restrict__ tw) {
   extern __shared__ float2 lds[];
@@ -822,23 +949,7 @@ __device__ __forceinline__ void row_c2r(const float2* X, float2* L, float2* v, i
 #pragma unroll
   for (int e = 0; e < E; ++e) xr[e] = gld(X + t + T * e);  // X: an in-bounds row for idle lanes
   xr[E] = gld(X + M);
-#pragma unroll
-  for (int e = 0; e < E; ++e) L[t + T * e] = xr[e];
-  if (t == 0) L[M] = xr[E];
-  zsync();
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int k = t + T * e;
-    float2 xa = L[k], xb = cconj(L[M - k]);
-    if (k == 0) {
-      xa = make_float2(L[0].x, 0.f);
-      xb = make_float2(L[M].x, 0.f);
-    }
-    const float2 s = cadd(xa, xb);
-    const float2 r = cmul(cconj(twN[k]), csub(xa, xb));
-    v[e] = make_float2(s.x - r.y, s.y + r.x);
-  }
-  zsync();
+  c2r_pre<N, T, E>(xr, v, L, t, twN);
   zfft<M, T, -1, typename C::RL>(v, L, t, active, twM);
 }
 
@@ -850,24 +961,7 @@ __device__ __forceinline__ void row_r2c(float2* v, float2* L, float2* X, int t, 
   using C = ZC<N>;
   constexpr int M = N / 2, T = C::T, E = M / T;
   zfft<M, T, +1, typename C::RL>(v, L, t, active, twM);
-  if (active) {
-#pragma unroll
-    for (int e = 0; e < E; ++e) L[t + T * e] = v[e];
-  }
-  zsync();
-  if (active) {
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int k = t + T * e;
-      const float2 zk = L[k];
-      const float2 zc = cconj(L[k == 0 ? 0 : M - k]);
-      const float2 ev = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y + zc.y));
-      const float2 df = csub(zk, zc);
-      const float2 od = make_float2(0.5f * df.y, -0.5f * df.x);
-      gst(X + k, cadd(ev, cmul(twN[k], od)));
-    }
-    if (t == 0) gst(X + M, make_float2(L[0].x - L[0].y, 0.f));
-  }
+  r2c_post<N, T, E>(v, L, t, active, twN, [&](int k, float2 x) { gst(X + k, x); });
   zsync();
 }
 
