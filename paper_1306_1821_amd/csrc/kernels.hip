@@ -68,6 +68,22 @@
 #ifndef HMC_ZDPP
 #define HMC_ZDPP 1
 #endif
+// twiddle table pointer made opaque per tile (HMC_ZTWO: real-space pass;
+// HMC_XTWO: k-space passes other than the step): the compiler then reloads the
+// twiddles of each tile (cache hits) instead of holding them in registers across
+// the tile loop
+#ifndef HMC_ZTWO
+#define HMC_ZTWO 1
+#endif
+#ifndef HMC_XTWO
+#define HMC_XTWO 0
+#endif
+// twiddles of the single-size real-space pass read from LDS (HMC_ZTWL): their
+// reads then leave the in-order vector-memory counter to the data loads, so the
+// alpha, beta prefetch stays in flight through the first transform
+#ifndef HMC_ZTWL
+#define HMC_ZTWL 1
+#endif
 #ifndef HMC_ZOCC
 #define HMC_ZOCC 1
 #endif
@@ -428,16 +444,16 @@ __device__ __forceinline__ int shell_q(uint64_t q, int n, int nb) {
 // The same rule evaluated in 32-bit integers with one float square root (exact for
 // N <= 256, nb <= 128: nb^2 q and (m+1)^2 q_max stay below 2^31); the square root
 // lands within one of the answer and one integer comparison each way corrects it.
+// Branch-free: the hardware square root (about 1 ulp) gives t within one of the
+// exact ceiling; one integer comparison each way corrects it.  No divergent
+// branches, so the compiler can issue the loads of every element up front.
 __device__ __forceinline__ int shell_fast(uint32_t q, uint32_t qmax, float inv_qmax, uint32_t nb) {
-  if (q == 0) return -1;
   const uint32_t lhs = nb * nb * q;
-  int t = (int)ceilf(sqrtf((float)lhs * inv_qmax));
+  int t = (int)ceilf(__builtin_amdgcn_sqrtf((float)lhs * inv_qmax));
   t = t < 1 ? 1 : t;
-  if ((uint32_t)(t * t) * qmax < lhs)
-    ++t;
-  else if (t > 1 && (uint32_t)((t - 1) * (t - 1)) * qmax >= lhs)
-    --t;
-  return t - 1;
+  t += (uint32_t)(t * t) * qmax < lhs ? 1 : 0;
+  t -= ((t > 1) & ((uint32_t)((t - 1) * (t - 1)) * qmax >= lhs)) ? 1 : 0;
+  return q == 0 ? -1 : t - 1;
 }
 __device__ __forceinline__ int shell_of(const ChainDev& d, int fx, int fy, int fz) {
   return shell_lut(d.lut, fx * fx + fy * fy + fz * fz);
@@ -732,7 +748,9 @@ k_xpass_n(const ChainDev* __restrict__ ch, int nch,
     const int tile = w.cur;
     const int c = find_chain(ch, nch, tile, kTileXY);
     const ChainDev& d = ch[c];
-    xpass<N, MODE>(d, tile - d.tb[kTileXY], a, tw, lds, red, bins);
+    const float2* twi = tw;
+    if constexpr (HMC_XTWO != 0 && MODE != X_STEP) asm volatile("" : "+s"(twi));
+    xpass<N, MODE>(d, tile - d.tb[kTileXY], a, twi, lds, red, bins);
   }
 }
 
@@ -792,13 +810,12 @@ __global__ void __launch_bounds__(kThreads) k_ypass_n(const ChainDev* __restrict
 }
 
 // ------------------------------------------------------------------ z pass
+// twM: W_M^i (i < M), twN: W_N^k (k < M), in global memory or staged in LDS
 template <int N, int MODE>
-__device__ __forceinline__ void zpass(const ChainDev& d, int lt, const ZArgs a, const float2* __restrict__ twall,
-                      float2* lds, double* red) {
+__device__ __forceinline__ void zpass_t(const ChainDev& d, int lt, const ZArgs a, const float2* twM,
+                                        const float2* twN, float2* lds, double* red) {
   using C = ZC<N>;
   constexpr int M = N / 2, T = C::T, B = C::B, E = M / T, H = M + 1, RS = zrs<N>();
-  const float2* twM = twall + tw_offset(M);
-  const float2* twN = twall + tw_offset(N);
   const int tid = threadIdx.x, t = tid % T, b = tid / T;
   const int row = lt * B + b;
   const bool active = row < N * N;
@@ -888,6 +905,12 @@ __device__ __forceinline__ void zpass(const ChainDev& d, int lt, const ZArgs a, 
   zsync();
 }
 
+template <int N, int MODE>
+__device__ __forceinline__ void zpass(const ChainDev& d, int lt, const ZArgs a,
+                                      const float2* __restrict__ twall, float2* lds, double* red) {
+  zpass_t<N, MODE>(d, lt, a, twall + tw_offset(N / 2), twall + tw_offset(N), lds, red);
+}
+
 template <int MODE>
 __global__ void __launch_bounds__(kThreads) k_zpass(const ChainDev* __restrict__ ch, int nch,
                                                      int total, ZArgs a,
@@ -918,11 +941,24 @@ k_zpass_n(const ChainDev* __restrict__ ch, int nch,
                                                        const float2* __restrict__ tw) {
   extern __shared__ float2 lds[];
   __shared__ double red[4];
+#if HMC_ZTWL
+  // the pass's twiddles staged in LDS once per workgroup: W_M^i, then W_N^k (k < M)
+  __shared__ float2 stw[N];
+  for (int i = threadIdx.x; i < N; i += kThreads)
+    stw[i] = i < N / 2 ? tw[tw_offset(N / 2) + i] : tw[tw_offset(N) + i - N / 2];
+  __syncthreads();
+#endif
   for (TileWalk w = tile_walk(total); w.cur < w.end; w.cur += w.step) {
     const int tile = w.cur;
     const int c = find_chain(ch, nch, tile, kTileZ);
     const ChainDev& d = ch[c];
-    zpass<N, MODE>(d, tile - d.tb[kTileZ], a, tw, lds, red);
+#if HMC_ZTWL
+    zpass_t<N, MODE>(d, tile - d.tb[kTileZ], a, stw, stw + N / 2, lds, red);
+#else
+    const float2* twi = tw;
+    if constexpr (HMC_ZTWO != 0) asm volatile("" : "+s"(twi));
+    zpass<N, MODE>(d, tile - d.tb[kTileZ], a, twi, lds, red);
+#endif
   }
 }
 

@@ -1,5 +1,5 @@
 """The k-shell rule as the k-space passes evaluate it (32-bit integers and one
-float32 square root, corrected by one integer comparison each way) equals the
+float32 square root, then one integer correction upwards and one downwards) equals the
 integer rule of the oracle for every q at every supported grid size, also when
 the square root is off by up to two units in the last place."""
 import numpy as np
@@ -17,9 +17,8 @@ def fast_rule(q, n, nb, ulps):
     for _ in range(abs(ulps)):
         s = np.nextafter(s, np.float32(np.inf) if ulps > 0 else np.float32(-np.inf))
     t = np.maximum(np.ceil(s).astype(np.int64), 1).astype(np.uint64)
-    up = t * t * qmax < lhs
-    down = (~up) & (t > 1) & ((t - 1) * (t - 1) * qmax >= lhs)
-    t = np.where(up, t + 1, np.where(down, t - 1, t))
+    t = np.where(t * t * qmax < lhs, t + 1, t)
+    t = np.where((t > 1) & ((t - 1) * (t - 1) * qmax >= lhs), t - 1, t)
     out = t.astype(np.int64) - 1
     return np.where(q == 0, -1, out)
 
