@@ -27,8 +27,12 @@ namespace hmcfft {
 
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+// Complex product with the fused multiply-adds written out: left to contraction,
+// which of the two products gets fused depends on how the operands reach the
+// expression (a load in the same block or a register from outside), so the same
+// source could round differently in two kernels.
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
-  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+  return make_float2(__builtin_fmaf(a.x, b.x, -(a.y * b.y)), __builtin_fmaf(a.x, b.y, a.y * b.x));
 }
 __device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
 __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
@@ -74,7 +78,7 @@ __device__ __forceinline__ float2 ctw(float2 v) {
     constexpr float c = (float)cx_twc(m, R);
     constexpr float s = (float)(-cx_tws(m, R));  // exp(-i a) = cos a - i sin a
     constexpr float sd = DIR > 0 ? s : -s;
-    return make_float2(v.x * c - v.y * sd, v.x * sd + v.y * c);
+    return make_float2(__builtin_fmaf(v.x, c, -(v.y * sd)), __builtin_fmaf(v.x, sd, v.y * c));
   }
 }
 
