@@ -298,7 +298,7 @@ def main():
         s.sweep(sweep)
         sweep += 1
     torch.cuda.synchronize()
-    s.timing(0x11)                      # HIP events around the k-space step passes only
+    s.timing(0x411)                     # HIP events around every 5th k-space step pass
     acc, rj_acc = [], []
     t0 = time.perf_counter()
     for _ in range(args.steps):

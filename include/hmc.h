@@ -265,13 +265,16 @@ hmc_status hmc_use_graph(hmc_ctx* ctx, int32_t enable);
 
 /* Device timing of the leapfrog passes (tracing).  enable = 1 starts
  * recording HIP events on the context's stream around every launch of the
- * step passes and clears the totals; enable = 0x10 | mask does the same for the
- * classes whose bits (1 << class) are set in mask (fewer events, less
- * perturbation); enable = 0 stops recording; enable = -1 only reads.  ms[4] / launches[4] (host, may be NULL) receive the summed
+ * step passes and clears the totals; enable = 0x10 | mask | (s << 8) does the
+ * same for the classes whose bits (1 << class) are set in mask, around every
+ * (s + 1)-th launch of each class only (s < 256; fewer events, less
+ * perturbation); enable = 0 stops recording; enable = -1 only reads.  Other
+ * values leave the state unchanged.  ms[4] / launches[4] (host, may be NULL)
+ * receive the summed
  * durations and launch counts of: [0] k-space passes of interior leapfrog
  * steps (kick, drift and both x transforms), [1] y passes, [2] real-space
- * passes (z transforms and the data force), [3] every other pass kernel.
- * Reading synchronises the stream. */
+ * passes (z transforms and the data force), [3] every other pass kernel, over
+ * the timed launches.  Reading synchronises the stream. */
 hmc_status hmc_timing(hmc_ctx* ctx, int32_t enable, double* ms, int64_t* launches);
 
 /* Static description of the last error on this context (or of the last

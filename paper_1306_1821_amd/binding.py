@@ -339,7 +339,8 @@ class Sampler:
     def timing(self, enable=-1):
         """Summed device milliseconds and launch counts of the step passes
         ([0] interior k-space passes, [1] y passes, [2] real-space passes, [3] other).
-        enable: 1 all classes, 0x10 | mask a subset, 0 stop, -1 read only."""
+        enable: 1 all classes, 0x10 | mask | (s << 8) a subset, every (s+1)-th
+        launch of a class, 0 stop, -1 read only."""
         ms = (ctypes.c_double * 4)()
         n = (ctypes.c_int64 * 4)()
         self._check(self.L.hmc_timing(self.ctx, int(enable), ms, n))

@@ -121,6 +121,8 @@ struct hmc_ctx {
   // pass timing (hmc_timing)
   bool timing = false;
   int timing_mask = 0xf;  // pass classes that record events
+  int timing_stride = 1;  // events around every timing_stride-th launch of a class
+  long long timing_seen[4] = {0, 0, 0, 0};
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_used;
   double t_ms[4] = {0, 0, 0, 0};
@@ -177,6 +179,7 @@ struct Timed {
   hipEvent_t a = nullptr, b = nullptr;
   Timed(hmc_ctx* c_, int kind_, hipStream_t s) : c(c_), kind(kind_) {
     if (!c->timing || !(c->timing_mask & (1 << kind))) return;
+    if (c->timing_seen[kind]++ % c->timing_stride != 0) return;
     a = ev_get(c);
     b = ev_get(c);
     if (a) (void)hipEventRecord(a, s);
@@ -1068,13 +1071,15 @@ hmc_status hmc_timing(hmc_ctx* c, int32_t enable, double* ms, int64_t* launches)
     if (ms) ms[i] = c->t_ms[i];
     if (launches) launches[i] = c->t_n[i];
   }
-  if (enable == 1 || (enable & ~0xf) == 0x10) {
+  if (enable == 1 || (enable >= 0x10 && enable < 0x10000 && (enable & 0xf0) == 0x10)) {
     for (int i = 0; i < 4; ++i) {
       c->t_ms[i] = 0.0;
       c->t_n[i] = 0;
+      c->timing_seen[i] = 0;
     }
     c->timing = true;
     c->timing_mask = enable == 1 ? 0xf : (enable & 0xf);
+    c->timing_stride = enable == 1 ? 1 : ((enable >> 8) & 0xff) + 1;
   } else if (enable == 0) {
     c->timing = false;
   }

@@ -197,3 +197,30 @@ def test_async_calls_equal_synchronous_ones():
         assert np.array_equal(a.state(i)["delta_k"], b.state(i)["delta_k"])
     a.close()
     b.close()
+
+
+def test_pass_timing_classes_and_sampling():
+    """Pass timing counts launches per class; a class mask records only those
+    classes and a sampling stride every stride-th launch of each; timing does
+    not change results."""
+    m = mock("cfg1")
+    nsteps = 8
+    runs = {}
+    for enable in (0, 1, 0x11, 0x411):
+        s = Sampler([chain_spec(m, eps=0.05, nsteps=nsteps, seed=5)])
+        s.set_state(0, start_state(m)[0])
+        if enable:
+            s.timing(enable)
+        res = [s.trajectory(i) for i in range(3)]
+        ms, n = s.timing(0)
+        runs[enable] = (res, n, ms, s.state(0)["delta_k"])
+        s.close()
+    interior = runs[1][1][0]
+    assert interior > 0 and runs[1][1][1] > 0 and runs[1][1][2] > 0
+    assert np.all(runs[1][2][runs[1][1] > 0] > 0)
+    assert runs[0x11][1][0] == interior and np.all(runs[0x11][1][1:] == 0)
+    assert runs[0x411][1][0] == (interior + 4) // 5 and np.all(runs[0x411][1][1:] == 0)
+    for enable in (1, 0x11, 0x411):
+        assert np.array_equal(runs[enable][3], runs[0][3])
+        for a, b in zip(runs[enable][0], runs[0][0]):
+            assert a[0][0] == b[0][0] and a[1][0] == b[1][0]
