@@ -60,8 +60,8 @@
 // real-space force pass (HMC_ZOCC), the k-space forward pass (HMC_XFOCC) and
 // the k-space step pass (HMC_XSOCC); 1 leaves register allocation free
 // z pass: padded LDS rows for the transform exchanges (HMC_ZLPAD) and the
-// real-transform partner exchange X_k <-> X_{M-k} by DPP lane moves inside a row
-// of 16 lanes instead of an LDS round trip (HMC_ZDPP, rows of 16 threads)
+// real-transform partner exchange X_k <-> X_{M-k} by DPP lane moves inside the
+// row's lanes instead of an LDS round trip (HMC_ZDPP)
 #ifndef HMC_ZLPAD
 #define HMC_ZLPAD 1
 #endif
@@ -255,15 +255,33 @@ __device__ __forceinline__ void zfft(float2* v, float2* lds, int t, bool active,
 #endif
 }
 
-// Inside each row of 16 lanes: lane t >= 1 receives `src` of lane 16 - t, lane 0
-// keeps `own` (DPP row_mirror, then row_shr:1, whose lane 0 has no source and keeps
-// the old value).
-__device__ __forceinline__ float dpp_partner16(float own, float src) {
-  const int m = __builtin_amdgcn_update_dpp(0, __float_as_int(src), 0x140, 0xf, 0xf, false);
-  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(own), m, 0x111, 0xf, 0xf, false));
+// Real-transform partner of a row held by T consecutive lanes (T divides 16, rows
+// aligned to T lanes): lane t >= 1 receives `src` of lane T - t of its row, lane 0
+// keeps `own`.  T = 16: DPP row_mirror, then row_shr:1 (whose lane 0 has no source
+// and keeps the old value); T = 8: row_half_mirror, row_shr:1 and a select for the
+// second half's lane 0; T = 4: quad_perm [0,3,2,1]; T <= 2: lane T - t is the lane
+// itself.
+template <int T>
+__device__ __forceinline__ float row_partner(float own, float src, int t) {
+  const int o = __float_as_int(own), v = __float_as_int(src);
+  if constexpr (T == 16) {
+    const int m = __builtin_amdgcn_update_dpp(0, v, 0x140, 0xf, 0xf, false);
+    return __int_as_float(__builtin_amdgcn_update_dpp(o, m, 0x111, 0xf, 0xf, false));
+  } else if constexpr (T == 8) {
+    const int m = __builtin_amdgcn_update_dpp(0, v, 0x141, 0xf, 0xf, false);
+    const int r = __builtin_amdgcn_update_dpp(o, m, 0x111, 0xf, 0xf, false);
+    return t == 0 ? own : __int_as_float(r);
+  } else if constexpr (T == 4) {
+    const int r = __builtin_amdgcn_update_dpp(0, v, 0x6c, 0xf, 0xf, false);
+    return t == 0 ? own : __int_as_float(r);
+  } else {
+    static_assert(T == 1 || T == 2, "row partner: T must divide 16");
+    return t == 0 ? own : src;
+  }
 }
-__device__ __forceinline__ float2 dpp_partner16(float2 own, float2 src) {
-  return make_float2(dpp_partner16(own.x, src.x), dpp_partner16(own.y, src.y));
+template <int T>
+__device__ __forceinline__ float2 row_partner(float2 own, float2 src, int t) {
+  return make_float2(row_partner<T>(own.x, src.x, t), row_partner<T>(own.y, src.y, t));
 }
 
 // Real transform of length N = 2M through a complex one of length M, row held
@@ -272,16 +290,16 @@ __device__ __forceinline__ float2 dpp_partner16(float2 own, float2 src) {
 //   Z_k = (X_k + conj X_{M-k}) + i W_N^-k (X_k - conj X_{M-k}),
 // dropping the imaginary parts of the self-conjugate X_0 and X_M.  X_{M-k} sits
 // in lane T - t as element E-1-e (t >= 1) and in lane 0 itself as element E - e;
-// rows of 16 lanes fetch it by DPP, others through the LDS row L.
+// fetched by DPP lane moves (HMC_ZDPP), else through the LDS row L.
 template <int N, int T, int E>
 __device__ __forceinline__ void c2r_pre(const float2* xr, float2* v, float2* L, int t,
                                         const float2* __restrict__ twN) {
   constexpr int M = N / 2;
-  if constexpr (HMC_ZDPP && T == 16) {
+  if constexpr (HMC_ZDPP) {
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int k = t + T * e;
-      float2 xa = xr[e], xb = cconj(dpp_partner16(xr[E - e], xr[E - 1 - e]));
+      float2 xa = xr[e], xb = cconj(row_partner<T>(xr[E - e], xr[E - 1 - e], t));
       if (k == 0) {
         xa = make_float2(xr[0].x, 0.f);
         xb = make_float2(xr[E].x, 0.f);
@@ -320,9 +338,9 @@ __device__ __forceinline__ void r2c_post(const float2* v, float2* L, int t, bool
                                          const float2* __restrict__ twN, Store st) {
   constexpr int M = N / 2;
   float2 zcv[E];
-  if constexpr (HMC_ZDPP && T == 16) {
+  if constexpr (HMC_ZDPP) {
 #pragma unroll
-    for (int e = 0; e < E; ++e) zcv[e] = cconj(dpp_partner16(v[(E - e) % E], v[E - 1 - e]));
+    for (int e = 0; e < E; ++e) zcv[e] = cconj(row_partner<T>(v[(E - e) % E], v[E - 1 - e], t));
   } else {
     if (active) {
 #pragma unroll
