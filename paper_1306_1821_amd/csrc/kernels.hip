@@ -56,9 +56,6 @@
 #ifndef HMC_XCD
 #define HMC_XCD 1
 #endif
-// minimum resident waves per SIMD asked of the compiler for the single-size
-// real-space force pass (HMC_ZOCC), the k-space forward pass (HMC_XFOCC) and
-// the k-space step pass (HMC_XSOCC); 1 leaves register allocation free
 // z pass: padded LDS rows for the transform exchanges (HMC_ZLPAD) and the
 // real-transform partner exchange X_k <-> X_{M-k} by DPP lane moves inside the
 // row's lanes instead of an LDS round trip (HMC_ZDPP)
@@ -68,30 +65,12 @@
 #ifndef HMC_ZDPP
 #define HMC_ZDPP 1
 #endif
-// twiddle table pointer made opaque per tile (HMC_ZTWO: real-space pass;
-// HMC_XTWO: k-space passes other than the step): the compiler then reloads the
-// twiddles of each tile (cache hits) instead of holding them in registers across
-// the tile loop
-#ifndef HMC_ZTWO
-#define HMC_ZTWO 1
-#endif
-#ifndef HMC_XTWO
-#define HMC_XTWO 0
-#endif
 // twiddles of the single-size real-space pass read from LDS (HMC_ZTWL): their
 // reads then leave the in-order vector-memory counter to the data loads, so the
-// alpha, beta prefetch stays in flight through the first transform
+// alpha, beta prefetch stays in flight through the first transform, and they are
+// not held in registers across the tile loop
 #ifndef HMC_ZTWL
 #define HMC_ZTWL 1
-#endif
-#ifndef HMC_ZOCC
-#define HMC_ZOCC 1
-#endif
-#ifndef HMC_XFOCC
-#define HMC_XFOCC 1
-#endif
-#ifndef HMC_XSOCC
-#define HMC_XSOCC 1
 #endif
 
 namespace hmc {
@@ -746,13 +725,9 @@ __global__ void __launch_bounds__(kThreads) k_xpass(const ChainDev* __restrict__
   }
 }
 
-template <int MODE> struct XOcc {
-  static constexpr int w = MODE == X_FWD ? HMC_XFOCC : MODE == X_STEP ? HMC_XSOCC : 1;
-};
 // single-size variant: every chain of the launch has this N (lower register use)
 template <int N, int MODE>
-__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(XOcc<MODE>::w)))
-k_xpass_n(const ChainDev* __restrict__ ch, int nch,
+__global__ void __launch_bounds__(kThreads) k_xpass_n(const ChainDev* __restrict__ ch, int nch,
                                                        int total, XArgs a,
                                                        const float2* __restrict__ tw) {
   extern __shared__ float2 lds[];
@@ -766,9 +741,7 @@ k_xpass_n(const ChainDev* __restrict__ ch, int nch,
     const int tile = w.cur;
     const int c = find_chain(ch, nch, tile, kTileXY);
     const ChainDev& d = ch[c];
-    const float2* twi = tw;
-    if constexpr (HMC_XTWO != 0 && MODE != X_STEP) asm volatile("" : "+s"(twi));
-    xpass<N, MODE>(d, tile - d.tb[kTileXY], a, twi, lds, red, bins);
+    xpass<N, MODE>(d, tile - d.tb[kTileXY], a, tw, lds, red, bins);
   }
 }
 
@@ -949,12 +922,8 @@ __global__ void __launch_bounds__(kThreads) k_zpass(const ChainDev* __restrict__
   }
 }
 
-template <int MODE> struct ZOcc {
-  static constexpr int w = MODE == Z_GRAD ? HMC_ZOCC : 1;
-};
 template <int N, int MODE>
-__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(ZOcc<MODE>::w)))
-k_zpass_n(const ChainDev* __restrict__ ch, int nch,
+__global__ void __launch_bounds__(kThreads) k_zpass_n(const ChainDev* __restrict__ ch, int nch,
                                                        int total, ZArgs a,
                                                        const float2* __restrict__ tw) {
   extern __shared__ float2 lds[];
@@ -973,9 +942,7 @@ k_zpass_n(const ChainDev* __restrict__ ch, int nch,
 #if HMC_ZTWL
     zpass_t<N, MODE>(d, tile - d.tb[kTileZ], a, stw, stw + N / 2, lds, red);
 #else
-    const float2* twi = tw;
-    if constexpr (HMC_ZTWO != 0) asm volatile("" : "+s"(twi));
-    zpass<N, MODE>(d, tile - d.tb[kTileZ], a, twi, lds, red);
+    zpass<N, MODE>(d, tile - d.tb[kTileZ], a, tw, lds, red);
 #endif
   }
 }
