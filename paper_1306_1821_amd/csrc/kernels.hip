@@ -589,7 +589,7 @@ __device__ __forceinline__ void xpass(const ChainDev& d, int lt, const XArgs a, 
       const float2 x = gldi(dkb, offs(e));
       float s = norm;
       if ((a.flags & XF_SCALE) && me >= 0) s *= tf[kTScale + me];
-      if ((a.flags & XF_PRIOR) && me >= 0) s *= (float)sqrt(gldd(d.P + kLam + me));
+      if ((a.flags & XF_PRIOR) && me >= 0) s *= rsqrtf(tf[kTInvLam + me]);  // sqrt(lambda_m)
       v[e] = me < 0 ? make_float2(0.f, 0.f) : cscale(x, s);
     }
   } else if constexpr (MODE == X_FWD) {
