@@ -129,6 +129,7 @@ def batched_main(args):
         s.sweep(sweep)
         sweep += 1
     chosen = s.autotune(10)
+    plans = s.launch_config()[1]
     s.use_graph(True)
     s.sweep(sweep)                       # capture
     sweep += 1
@@ -175,6 +176,7 @@ def batched_main(args):
         "voxels": vox,
         "equivalent_256_steps_per_s": value / len(specs) * vox / 256 ** 3,
         "launch_grids": chosen,
+        "radix_plans": plans,
         "acceptance": float(np.mean(acc)),
         "split_rhat_lnP": rhat,
     }

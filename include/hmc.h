@@ -209,13 +209,31 @@ hmc_status hmc_warm_start(hmc_ctx* ctx, int32_t chain, const float* mu_dev,
  * every chain has one size).  Results do not depend on it. */
 hmc_status hmc_set_launch(hmc_ctx* ctx, int32_t pass_class, int32_t grid);
 
+/* Radix plan of the transforms of a pass class (0 the k-space step pass, 1 the
+ * y passes, 2 the real-space force pass) in single-size launches of grids of
+ * 64^3, 128^3, 192^3 and 256^3: plan 0 (default) or one of two alternative
+ * factorisations of the same pencil shape (same tiles, LDS and memory access;
+ * different stage counts and LDS exchanges), 0 <= plan < 3.  Other grid sizes
+ * and mixed-size launches use plan 0.  A plan changes the rounding of the
+ * transforms (results agree with plan 0 to float32 rounding, not bitwise);
+ * results are reproducible for a fixed plan.  Captured graphs are dropped.
+ * HMC_EINVAL on a bad class or plan. */
+hmc_status hmc_set_plan(hmc_ctx* ctx, int32_t pass_class, int32_t plan);
+
+/* The launch configuration in force: grid[3] in the form hmc_set_launch takes,
+ * plan[3] as hmc_set_plan (host arrays, either may be NULL). */
+hmc_status hmc_get_launch(hmc_ctx* ctx, int32_t* grid, int32_t* plan);
+
 /* Autotuner of the launch shapes: for each pass class, times `reps` launches of
  * each candidate (for mixed-size batches one launch per size group, then one
  * launch over the batch with one workgroup per tile or 2, 3, 4, 5, 6, 8, 12
  * workgroups per compute unit) on the context's chains with HIP events and keeps
- * the fastest; chosen (host [3], may be NULL) receives the grids in the form
- * hmc_set_launch takes.  The state
- * (delta_hat, p_hat, the parameters) is unchanged; captured graphs are dropped. */
+ * the fastest, then, when the chosen launches are single-size and a grid size
+ * has alternative plans, times plans 1 and 2 at that grid and keeps the fastest
+ * of the three (hmc_set_plan: a plan other than 0 changes rounding); chosen
+ * (host [3], may be NULL) receives the grids in the form hmc_set_launch takes
+ * (hmc_get_launch also returns the plans).  The state (delta_hat, p_hat, the
+ * parameters) is unchanged; captured graphs are dropped. */
 hmc_status hmc_autotune(hmc_ctx* ctx, int32_t reps, int32_t* chosen);
 
 /* Change the leapfrog step size eps of chain `chain` (the same eps also steps

@@ -44,7 +44,7 @@ class HmcSweepStats(ctypes.Structure):
 EXPORTS = ["hmc_workspace_bytes", "hmc_init", "hmc_init_batch", "leapfrog_trajectory",
            "leapfrog_trajectory_async", "gibbs_sweep_async", "hmc_sweep_record_doubles",
            "hamiltonian", "shell_power", "gibbs_sweep", "hmc_set_state", "hmc_set_params",
-           "hmc_set_step", "hmc_warm_start", "hmc_set_launch", "hmc_autotune", "hmc_set_coefficients", "hmc_get_params", "hmc_shell_index", "hmc_set_mass",
+           "hmc_set_step", "hmc_warm_start", "hmc_set_launch", "hmc_set_plan", "hmc_get_launch", "hmc_autotune", "hmc_set_coefficients", "hmc_get_params", "hmc_shell_index", "hmc_set_mass",
            "hmc_timing", "hmc_use_graph", "hmc_last_error", "hmc_destroy",
            "cnn_param_count", "cnn_create", "cnn_get_params", "cnn_forward", "cnn_gradient",
            "cnn_features",
@@ -85,6 +85,8 @@ def lib(path=LIB_PATH):
     L.hmc_warm_start.argtypes = [P, I32, P, P, U64]
     L.hmc_set_launch.argtypes = [P, I32, I32]
     L.hmc_autotune.argtypes = [P, I32, ctypes.POINTER(I32)]
+    L.hmc_set_plan.argtypes = [P, I32, I32]
+    L.hmc_get_launch.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I32)]
     L.hmc_set_coefficients.argtypes = [P, I32, P, P]
     L.hmc_get_params.argtypes = [P, I32, D, D, D]
     L.hmc_shell_index.argtypes = [P, I32, P]
@@ -326,8 +328,20 @@ class Sampler:
         -1: one launch per grid size of a mixed-size batch."""
         self._check(self.L.hmc_set_launch(self.ctx, int(pass_class), int(grid)))
 
+    def set_plan(self, pass_class, plan):
+        """Radix plan (0, 1, 2) of a pass class's transforms in single-size launches
+        of 64^3 .. 256^3 grids; plans other than 0 change rounding."""
+        self._check(self.L.hmc_set_plan(self.ctx, int(pass_class), int(plan)))
+
+    def launch_config(self):
+        """(grids, plans) in force, three of each (pass classes x, y, z)."""
+        g, p = (ctypes.c_int32 * 3)(), (ctypes.c_int32 * 3)()
+        self._check(self.L.hmc_get_launch(self.ctx, g, p))
+        return list(g), list(p)
+
     def autotune(self, reps=10):
-        """Pick the fastest launch grid per pass class; returns the three grids."""
+        """Pick the fastest launch grid (then radix plan) per pass class; returns the
+        three grids (launch_config() also gives the plans)."""
         out = (ctypes.c_int32 * 3)()
         self._check(self.L.hmc_autotune(self.ctx, int(reps), out))
         return list(out)

@@ -202,6 +202,32 @@ template <> struct ZC<256> { static constexpr int T = 32, B = 8;  using RL = Rad
 template <> struct ZC<256> { static constexpr int T = 8, B = 32;  using RL = Radices<16, 8>; };
 #endif
 
+// Radix plans of the single-size step passes.  Every plan keeps the pencil shape
+// (T threads, B pencils per workgroup), so tiles, LDS size and the memory access
+// pattern are the plan-independent; the transform's stage count and LDS exchanges
+// differ.  Plan 0 is the shape's default list; grids of 64^3 and more have two
+// alternatives that the autotuner times (hmc_autotune / hmc_set_plan).
+
+template <int N> constexpr bool has_plans() { return N == 64 || N == 128 || N == 192 || N == 256; }
+template <int N, int P> struct XPlan { using RL = typename XC<N>::RL; };
+template <> struct XPlan<64, 1>  { using RL = Radices<4, 4, 4>; };
+template <> struct XPlan<64, 2>  { using RL = Radices<2, 4, 8>; };
+template <> struct XPlan<128, 1> { using RL = Radices<8, 16>; };
+template <> struct XPlan<128, 2> { using RL = Radices<4, 4, 8>; };
+template <> struct XPlan<192, 1> { using RL = Radices<12, 4, 4>; };
+template <> struct XPlan<192, 2> { using RL = Radices<4, 12, 4>; };
+template <> struct XPlan<256, 1> { using RL = Radices<4, 4, 16>; };
+template <> struct XPlan<256, 2> { using RL = Radices<8, 8, 4>; };
+template <int N, int P> struct ZPlan { using RL = typename ZC<N>::RL; };
+template <> struct ZPlan<64, 1>  { using RL = Radices<4, 8>; };
+template <> struct ZPlan<64, 2>  { using RL = Radices<2, 4, 4>; };
+template <> struct ZPlan<128, 1> { using RL = Radices<4, 4, 4>; };
+template <> struct ZPlan<128, 2> { using RL = Radices<2, 4, 8>; };
+template <> struct ZPlan<192, 1> { using RL = Radices<6, 4, 4>; };
+template <> struct ZPlan<192, 2> { using RL = Radices<4, 6, 4>; };
+template <> struct ZPlan<256, 1> { using RL = Radices<4, 4, 8>; };
+template <> struct ZPlan<256, 2> { using RL = Radices<2, 8, 8>; };
+
 template <int N> constexpr int xlds() { return N * (XC<N>::B + 1) * 8; }
 // z-pass LDS row stride in float2: at least M + 2; for M >= 64 rounded up to
 // 16 mod 32 so that the two rows a half-wave reads fall on disjoint LDS banks
@@ -522,10 +548,11 @@ __device__ __forceinline__ void bins_flush(B* bins, double* dst, int nb) {
 // col = tile B + b (ky = col / H, kz = col % H).  Idle lanes of the last tile read
 // column 0 (in bounds) and store nothing.  Every load of an element is issued
 // before its first use so that one wait covers them.
-template <int N, int MODE>
+template <int N, int MODE, int P = 0>
 __device__ __forceinline__ void xpass(const ChainDev& d, int lt, const XArgs a, const float2* __restrict__ twall,
                       float2* lds, double* red, bin_t* bins) {
   using C = XC<N>;
+  using RL = typename XPlan<N, P>::RL;
   constexpr int T = C::T, B = C::B, E = N / T, H = N / 2 + 1, ES = B + 1;
   constexpr uint32_t stride = (uint32_t)N * H;
   const float2* tw = twall + tw_offset(N);
@@ -578,7 +605,7 @@ __device__ __forceinline__ void xpass(const ChainDev& d, int lt, const XArgs a, 
   if constexpr (MODE != X_INV) {
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = gldi(Tb, offs(e));
-    fft<N, T, +1>(v, L, ES, t, active, tw, typename C::RL{});
+    fft<N, T, +1>(v, L, ES, t, active, tw, RL{});
   }
 
   double acc0 = 0.0, acc1 = 0.0;
@@ -682,7 +709,7 @@ __device__ __forceinline__ void xpass(const ChainDev& d, int lt, const XArgs a, 
   }
 
   if constexpr (MODE == X_INV || MODE == X_START || MODE == X_STEP) {
-    fft<N, T, -1>(v, L, ES, t, active, tw, typename C::RL{});
+    fft<N, T, -1>(v, L, ES, t, active, tw, RL{});
     if (active) {
 #pragma unroll
       for (int e = 0; e < E; ++e) gsti(Tb, offs(e), v[e]);
@@ -726,7 +753,7 @@ __global__ void __launch_bounds__(kThreads) k_xpass(const ChainDev* __restrict__
 }
 
 // single-size variant: every chain of the launch has this N (lower register use)
-template <int N, int MODE>
+template <int N, int MODE, int P = 0>
 __global__ void __launch_bounds__(kThreads) k_xpass_n(const ChainDev* __restrict__ ch, int nch,
                                                        int total, XArgs a,
                                                        const float2* __restrict__ tw) {
@@ -741,15 +768,16 @@ __global__ void __launch_bounds__(kThreads) k_xpass_n(const ChainDev* __restrict
     const int tile = w.cur;
     const int c = find_chain(ch, nch, tile, kTileXY);
     const ChainDev& d = ch[c];
-    xpass<N, MODE>(d, tile - d.tb[kTileXY], a, tw, lds, red, bins);
+    xpass<N, MODE, P>(d, tile - d.tb[kTileXY], a, tw, lds, red, bins);
   }
 }
 
 // ------------------------------------------------------------------ y pass
-template <int N, int DIR>
+template <int N, int DIR, int P = 0>
 __device__ __forceinline__ void ypass(const ChainDev& d, int lt, const float2* __restrict__ twall, float2* lds,
                                       int buf) {
   using C = XC<N>;
+  using RL = typename XPlan<N, P>::RL;
   constexpr int T = C::T, B = C::B, E = N / T, H = N / 2 + 1, ES = B + 1;
   const float2* tw = twall + tw_offset(N);
   const int tid = threadIdx.x, b = tid % B, t = tid / B;
@@ -761,7 +789,7 @@ __device__ __forceinline__ void ypass(const ChainDev& d, int lt, const float2* _
   float2 v[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) v[e] = gldi(base, o0 + (uint32_t)((t + T * e) * H));
-  fft<N, T, DIR>(v, lds + b, ES, t, active, tw, typename C::RL{});
+  fft<N, T, DIR>(v, lds + b, ES, t, active, tw, RL{});
   if (active) {
 #pragma unroll
     for (int e = 0; e < E; ++e) gsti(base, o0 + (uint32_t)((t + T * e) * H), v[e]);
@@ -787,7 +815,7 @@ __global__ void __launch_bounds__(kThreads) k_ypass(const ChainDev* __restrict__
   }
 }
 
-template <int N, int DIR>
+template <int N, int DIR, int P = 0>
 __global__ void __launch_bounds__(kThreads) k_ypass_n(const ChainDev* __restrict__ ch, int nch,
                                                        int total, const float2* __restrict__ tw,
                                                        int buf) {
@@ -796,16 +824,17 @@ __global__ void __launch_bounds__(kThreads) k_ypass_n(const ChainDev* __restrict
     const int tile = w.cur;
     const int c = find_chain(ch, nch, tile, kTileXY);
     const ChainDev& d = ch[c];
-    ypass<N, DIR>(d, tile - d.tb[kTileXY], tw, lds, buf);
+    ypass<N, DIR, P>(d, tile - d.tb[kTileXY], tw, lds, buf);
   }
 }
 
 // ------------------------------------------------------------------ z pass
 // twM: W_M^i (i < M), twN: W_N^k (k < M), in global memory or staged in LDS
-template <int N, int MODE>
+template <int N, int MODE, int P = 0>
 __device__ __forceinline__ void zpass_t(const ChainDev& d, int lt, const ZArgs a, const float2* twM,
                                         const float2* twN, float2* lds, double* red) {
   using C = ZC<N>;
+  using RL = typename ZPlan<N, P>::RL;
   constexpr int M = N / 2, T = C::T, B = C::B, E = M / T, H = M + 1, RS = zrs<N>();
   const int tid = threadIdx.x, t = tid % T, b = tid / T;
   const int row = lt * B + b;
@@ -841,7 +870,7 @@ __device__ __forceinline__ void zpass_t(const ChainDev& d, int lt, const ZArgs a
     for (int e = 0; e < E; ++e) xr[e] = gldi(Tb, xo + t + T * e);
     xr[E] = gldi(Tb, xo + M);
     c2r_pre<N, T, E>(xr, v, L, t, twN);
-    zfft<M, T, -1, typename C::RL>(v, L, t, active, twM);
+    zfft<M, T, -1, RL>(v, L, t, active, twM);
   } else if constexpr (MODE == Z_R2C) {
 #pragma unroll
     for (int e = 0; e < E; ++e)
@@ -886,7 +915,7 @@ __device__ __forceinline__ void zpass_t(const ChainDev& d, int lt, const ZArgs a
   }
 
   if constexpr (MODE != Z_C2R) {
-    zfft<M, T, +1, typename C::RL>(v, L, t, active, twM);
+    zfft<M, T, +1, RL>(v, L, t, active, twM);
     r2c_post<N, T, E>(v, L, t, active, twN, [&](int k, float2 x) { gsti(Tb, xo + k, x); });
   }
   if (a.flags & ZF_DATA) {
@@ -922,7 +951,7 @@ __global__ void __launch_bounds__(kThreads) k_zpass(const ChainDev* __restrict__
   }
 }
 
-template <int N, int MODE>
+template <int N, int MODE, int P = 0>
 __global__ void __launch_bounds__(kThreads) k_zpass_n(const ChainDev* __restrict__ ch, int nch,
                                                        int total, ZArgs a,
                                                        const float2* __restrict__ tw) {
@@ -940,9 +969,9 @@ __global__ void __launch_bounds__(kThreads) k_zpass_n(const ChainDev* __restrict
     const int c = find_chain(ch, nch, tile, kTileZ);
     const ChainDev& d = ch[c];
 #if HMC_ZTWL
-    zpass_t<N, MODE>(d, tile - d.tb[kTileZ], a, stw, stw + N / 2, lds, red);
+    zpass_t<N, MODE, P>(d, tile - d.tb[kTileZ], a, stw, stw + N / 2, lds, red);
 #else
-    zpass<N, MODE>(d, tile - d.tb[kTileZ], a, tw, lds, red);
+    zpass_t<N, MODE, P>(d, tile - d.tb[kTileZ], a, tw + tw_offset(N / 2), tw + tw_offset(N), lds, red);
 #endif
   }
 }
@@ -1320,22 +1349,62 @@ __global__ void __launch_bounds__(kThreads) k_warm_combine(const ChainDev* __res
 // ------------------------------------------------------------------ launches
 static inline int grid_of(int total, int cap) { return total < cap || cap <= 0 ? total : cap; }
 
+// plan: radix plan of the step pass (X_STEP), y passes and the force pass (Z_GRAD)
 template <int N>
 static void launch_x_n(int mode, dim3 g, dim3 bl, int lds, hipStream_t s, const ChainDev* ch,
-                       int nch, int total, XArgs a, const float2* tw) {
+                       int nch, int total, XArgs a, const float2* tw, int plan) {
   switch (mode) {
     case X_INV: hipLaunchKernelGGL((k_xpass_n<N, X_INV>), g, bl, lds, s, ch, nch, total, a, tw); break;
     case X_FWD: hipLaunchKernelGGL((k_xpass_n<N, X_FWD>), g, bl, lds, s, ch, nch, total, a, tw); break;
     case X_START: hipLaunchKernelGGL((k_xpass_n<N, X_START>), g, bl, lds, s, ch, nch, total, a, tw); break;
-    case X_STEP: hipLaunchKernelGGL((k_xpass_n<N, X_STEP>), g, bl, lds, s, ch, nch, total, a, tw); break;
+    case X_STEP:
+      if constexpr (has_plans<N>()) {
+        if (plan == 1) {
+          hipLaunchKernelGGL((k_xpass_n<N, X_STEP, 1>), g, bl, lds, s, ch, nch, total, a, tw);
+          break;
+        }
+        if (plan == 2) {
+          hipLaunchKernelGGL((k_xpass_n<N, X_STEP, 2>), g, bl, lds, s, ch, nch, total, a, tw);
+          break;
+        }
+      }
+      hipLaunchKernelGGL((k_xpass_n<N, X_STEP>), g, bl, lds, s, ch, nch, total, a, tw);
+      break;
     case X_END: hipLaunchKernelGGL((k_xpass_n<N, X_END>), g, bl, lds, s, ch, nch, total, a, tw); break;
   }
 }
+template <int N, int DIR>
+static void launch_y_n(dim3 g, dim3 bl, int lds, hipStream_t s, const ChainDev* ch, int nch,
+                       int total, const float2* tw, int buf, int plan) {
+  if constexpr (has_plans<N>()) {
+    if (plan == 1) {
+      hipLaunchKernelGGL((k_ypass_n<N, DIR, 1>), g, bl, lds, s, ch, nch, total, tw, buf);
+      return;
+    }
+    if (plan == 2) {
+      hipLaunchKernelGGL((k_ypass_n<N, DIR, 2>), g, bl, lds, s, ch, nch, total, tw, buf);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_ypass_n<N, DIR>), g, bl, lds, s, ch, nch, total, tw, buf);
+}
 template <int N>
 static void launch_z_n(int mode, dim3 g, dim3 bl, int lds, hipStream_t s, const ChainDev* ch,
-                       int nch, int total, ZArgs a, const float2* tw) {
+                       int nch, int total, ZArgs a, const float2* tw, int plan) {
   switch (mode) {
-    case Z_GRAD: hipLaunchKernelGGL((k_zpass_n<N, Z_GRAD>), g, bl, lds, s, ch, nch, total, a, tw); break;
+    case Z_GRAD:
+      if constexpr (has_plans<N>()) {
+        if (plan == 1) {
+          hipLaunchKernelGGL((k_zpass_n<N, Z_GRAD, 1>), g, bl, lds, s, ch, nch, total, a, tw);
+          break;
+        }
+        if (plan == 2) {
+          hipLaunchKernelGGL((k_zpass_n<N, Z_GRAD, 2>), g, bl, lds, s, ch, nch, total, a, tw);
+          break;
+        }
+      }
+      hipLaunchKernelGGL((k_zpass_n<N, Z_GRAD>), g, bl, lds, s, ch, nch, total, a, tw);
+      break;
     case Z_NOISE: hipLaunchKernelGGL((k_zpass_n<N, Z_NOISE>), g, bl, lds, s, ch, nch, total, a, tw); break;
     case Z_C2R: hipLaunchKernelGGL((k_zpass_n<N, Z_C2R>), g, bl, lds, s, ch, nch, total, a, tw); break;
     case Z_R2C: hipLaunchKernelGGL((k_zpass_n<N, Z_R2C>), g, bl, lds, s, ch, nch, total, a, tw); break;
@@ -1345,10 +1414,10 @@ static void launch_z_n(int mode, dim3 g, dim3 bl, int lds, hipStream_t s, const 
 // uniform_n > 0: every chain of the launch has that N (single-size kernels);
 // otherwise the mixed-size kernels dispatch per tile.
 void launch_xpass(int mode, const ChainDev* ch, int nch, int total, int lds, XArgs a,
-                  const float2* tw, int cap, hipStream_t s, int uniform_n) {
+                  const float2* tw, int cap, hipStream_t s, int uniform_n, int plan) {
   dim3 g(grid_of(total, cap)), bl(kThreads);
   switch (uniform_n) {
-#define C(NN) case NN: launch_x_n<NN>(mode, g, bl, lds, s, ch, nch, total, a, tw); return;
+#define C(NN) case NN: launch_x_n<NN>(mode, g, bl, lds, s, ch, nch, total, a, tw, plan); return;
     HMC_FOR_N(C)
 #undef C
     default: break;
@@ -1362,15 +1431,15 @@ void launch_xpass(int mode, const ChainDev* ch, int nch, int total, int lds, XAr
   }
 }
 void launch_ypass(int dir, const ChainDev* ch, int nch, int total, int lds, const float2* tw,
-                  int cap, hipStream_t s, int uniform_n, int buf) {
+                  int cap, hipStream_t s, int uniform_n, int buf, int plan) {
   dim3 g(grid_of(total, cap)), bl(kThreads);
   switch (uniform_n) {
-#define C(NN)                                                                          \
-  case NN:                                                                             \
-    if (dir > 0)                                                                       \
-      hipLaunchKernelGGL((k_ypass_n<NN, 1>), g, bl, lds, s, ch, nch, total, tw, buf);  \
-    else                                                                               \
-      hipLaunchKernelGGL((k_ypass_n<NN, -1>), g, bl, lds, s, ch, nch, total, tw, buf); \
+#define C(NN)                                                                  \
+  case NN:                                                                     \
+    if (dir > 0)                                                               \
+      launch_y_n<NN, 1>(g, bl, lds, s, ch, nch, total, tw, buf, plan);         \
+    else                                                                       \
+      launch_y_n<NN, -1>(g, bl, lds, s, ch, nch, total, tw, buf, plan);        \
     return;
     HMC_FOR_N(C)
 #undef C
@@ -1382,10 +1451,10 @@ void launch_ypass(int dir, const ChainDev* ch, int nch, int total, int lds, cons
     hipLaunchKernelGGL(k_ypass<-1>, g, bl, lds, s, ch, nch, total, tw, buf);
 }
 void launch_zpass(int mode, const ChainDev* ch, int nch, int total, int lds, ZArgs a,
-                  const float2* tw, int cap, hipStream_t s, int uniform_n) {
+                  const float2* tw, int cap, hipStream_t s, int uniform_n, int plan) {
   dim3 g(grid_of(total, cap)), bl(kThreads);
   switch (uniform_n) {
-#define C(NN) case NN: launch_z_n<NN>(mode, g, bl, lds, s, ch, nch, total, a, tw); return;
+#define C(NN) case NN: launch_z_n<NN>(mode, g, bl, lds, s, ch, nch, total, a, tw, plan); return;
     HMC_FOR_N(C)
 #undef C
     default: break;

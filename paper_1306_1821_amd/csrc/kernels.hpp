@@ -47,11 +47,15 @@ int zpass_tiles(int n);
 bool supported_n(int n);
 
 // launches (grid = total tiles of the class, capped at `grid_cap` blocks)
-// uniform_n: the N shared by every chain of the launch, or 0 for mixed sizes
+// uniform_n: the N shared by every chain of the launch, or 0 for mixed sizes;
+// plan: radix plan (0 .. kPlanCount - 1) of the single-size step pass (X_STEP),
+// y passes and force pass (Z_GRAD) for N >= 64; other launches use plan 0
+constexpr int kPlanCount = 3;
 void launch_xpass(int mode, const ChainDev* ch, int nch, int total, int lds, XArgs a,
-                  const float2* tw, int grid_cap, hipStream_t s, int uniform_n);
+                  const float2* tw, int grid_cap, hipStream_t s, int uniform_n, int plan = 0);
 void launch_ypass(int dir, const ChainDev* ch, int nch, int total, int lds, const float2* tw,
-                  int grid_cap, hipStream_t s, int uniform_n, int buf = 0);  // buf: T, T2, T3
+                  int grid_cap, hipStream_t s, int uniform_n, int buf = 0,
+                  int plan = 0);  // buf: T, T2, T3
 void launch_xpass_learned(int mode, const ChainDev* ch, int nch, int total, int lds, XArgs a,
                           const float2* tw, int grid_cap, hipStream_t s, int uniform_n);
 void launch_zpass_learned(int mode, const ChainDev* ch, int nch, int total, int lds, ZArgs a,
@@ -59,7 +63,7 @@ void launch_zpass_learned(int mode, const ChainDev* ch, int nch, int total, int 
 void launch_mass_prep(int phase, const ChainDev* ch, int total_r, const float* logvar,
                       hipStream_t s);
 void launch_zpass(int mode, const ChainDev* ch, int nch, int total, int lds, ZArgs a,
-                  const float2* tw, int grid_cap, hipStream_t s, int uniform_n);
+                  const float2* tw, int grid_cap, hipStream_t s, int uniform_n, int plan = 0);
 void launch_export(const ChainDev* ch, int nch, int sweep, double* rec, int32_t* acc,
                    hipStream_t s);
 void launch_shell_lut(const ChainDev* ch, int n, hipStream_t s);

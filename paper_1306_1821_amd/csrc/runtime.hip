@@ -116,6 +116,7 @@ struct hmc_ctx {
   };
   std::vector<Group> groups;
   bool grouped[3] = {false, false, false};  // per pass class (x, y, z)
+  int plan[3] = {0, 0, 0};  // radix plan per pass class for single-size launches
   bool learned = false;      // every chain runs the learned mass
   bool mass_mixed = false;   // some chains only have a learned mass: no trajectories
   // pass timing (hmc_timing)
@@ -211,14 +212,15 @@ struct Seq {
   void x(int mode, float kick, float drift, int flags) {
     Timed tm(c, mode == X_STEP ? 0 : 3, s);
     each(0, [&](const ChainDev* dd, int n, const int* t, int u, int g) {
-      launch_xpass(mode, dd, n, t[kTileXY], c->lds_x, XArgs{kick, drift, flags}, c->tw, g, s, u);
+      launch_xpass(mode, dd, n, t[kTileXY], c->lds_x, XArgs{kick, drift, flags}, c->tw, g, s, u,
+                   c->plan[0]);
     });
     tm.done(s);
   }
   void y(int dir, int buf = 0) {
     Timed tm(c, 1, s);
     each(1, [&](const ChainDev* dd, int n, const int* t, int u, int g) {
-      launch_ypass(dir, dd, n, t[kTileXY], c->lds_x, c->tw, g, s, u, buf);
+      launch_ypass(dir, dd, n, t[kTileXY], c->lds_x, c->tw, g, s, u, buf, c->plan[1]);
     });
     tm.done(s);
   }
@@ -241,7 +243,8 @@ struct Seq {
   void z(int mode, int flags, const float* src = nullptr) {
     Timed tm(c, mode == Z_GRAD ? 2 : 3, s);
     each(2, [&](const ChainDev* dd, int n, const int* t, int u, int g) {
-      launch_zpass(mode, dd, n, t[kTileZ], c->lds_z, ZArgs{flags, 0, src}, c->tw, g, s, u);
+      launch_zpass(mode, dd, n, t[kTileZ], c->lds_z, ZArgs{flags, 0, src}, c->tw, g, s, u,
+                   c->plan[2]);
     });
     tm.done(s);
   }
@@ -988,6 +991,32 @@ hmc_status hmc_set_launch(hmc_ctx* c, int32_t cls, int32_t grid) {
   return HMC_OK;
 }
 
+hmc_status hmc_set_plan(hmc_ctx* c, int32_t cls, int32_t plan) {
+  if (!c || cls < 0 || cls > 2 || plan < 0 || plan >= kPlanCount)
+    return fail(c, HMC_EINVAL, "bad argument");
+  c->plan[cls] = plan;
+  drop_graphs(c);
+  return HMC_OK;
+}
+
+hmc_status hmc_get_launch(hmc_ctx* c, int32_t* grid, int32_t* plan) {
+  if (!c) return fail(nullptr, HMC_EINVAL, "null context");
+  for (int cls = 0; cls < 3; ++cls) {
+    if (grid) grid[cls] = c->grouped[cls] ? -1 : c->grid[cls];
+    if (plan) plan[cls] = c->plan[cls];
+  }
+  return HMC_OK;
+}
+
+// true if some chain's grid size has alternative radix plans
+static bool any_plans(const hmc_ctx* c) {
+  for (auto& k : c->ch) {
+    const int n = k.cfg.n;
+    if (n == 64 || n == 128 || n == 192 || n == 256) return true;
+  }
+  return false;
+}
+
 // One launch of the pass class on every chain.  The k-space pass runs with zero
 // kick and drift (it rewrites delta_hat and p_hat with their own values); the y
 // and real-space passes only touch the intermediate grid, which no call expects
@@ -1014,10 +1043,21 @@ hmc_status hmc_autotune(hmc_ctx* c, int32_t reps, int32_t* chosen) {
   HIPCHK(c, hipEventCreate(&b));
   const int mult[] = {0, 2, 3, 4, 5, 6, 8, 12};
   hmc_status st = HMC_OK;
+  auto time_class = [&](int cls, float* ms) -> bool {
+    tune_launch(c, cls);  // warm-up
+    if (hipEventRecord(a, c->stream) != hipSuccess) return false;
+    for (int r = 0; r < reps; ++r) tune_launch(c, cls);
+    if (hipEventRecord(b, c->stream) != hipSuccess || hipEventSynchronize(b) != hipSuccess)
+      return false;
+    *ms = 0.f;
+    (void)hipEventElapsedTime(ms, a, b);
+    return true;
+  };
   for (int cls = 0; cls < 3 && st == HMC_OK; ++cls) {
     float best = 0.f;
     int best_grid = 0;
     bool best_grouped = false;
+    c->plan[cls] = 0;
     // candidates: one launch per size group (batches of several sizes), then one
     // launch over the whole batch with each grid
     for (int cand = c->groups.empty() ? 0 : -1; cand < (int)(sizeof(mult) / sizeof(int)); ++cand) {
@@ -1026,15 +1066,11 @@ hmc_status hmc_autotune(hmc_ctx* c, int32_t reps, int32_t* chosen) {
       if (!grp && mult[cand] > 0 && (grid >= class_tiles(c, cls) || grid % 8 != 0)) continue;
       c->grouped[cls] = grp;
       c->grid[cls] = grid;
-      tune_launch(c, cls);  // warm-up
-      if (hipEventRecord(a, c->stream) != hipSuccess) { st = HMC_EDEVICE; break; }
-      for (int r = 0; r < reps; ++r) tune_launch(c, cls);
-      if (hipEventRecord(b, c->stream) != hipSuccess || hipEventSynchronize(b) != hipSuccess) {
+      float ms = 0.f;
+      if (!time_class(cls, &ms)) {
         st = HMC_EDEVICE;
         break;
       }
-      float ms = 0.f;
-      (void)hipEventElapsedTime(&ms, a, b);
       if (best == 0.f || ms < best) {
         best = ms;
         best_grid = grid;
@@ -1044,6 +1080,23 @@ hmc_status hmc_autotune(hmc_ctx* c, int32_t reps, int32_t* chosen) {
     c->grid[cls] = best_grid;
     c->grouped[cls] = best_grouped;
     if (chosen) chosen[cls] = best_grouped ? -1 : best_grid;
+    // radix plans of the single-size launches at the chosen grid
+    if (st == HMC_OK && any_plans(c) && (c->uniform_n != 0 || best_grouped)) {
+      int best_plan = 0;
+      for (int p = 1; p < kPlanCount; ++p) {
+        c->plan[cls] = p;
+        float ms = 0.f;
+        if (!time_class(cls, &ms)) {
+          st = HMC_EDEVICE;
+          break;
+        }
+        if (ms < best) {
+          best = ms;
+          best_plan = p;
+        }
+      }
+      c->plan[cls] = best_plan;
+    }
   }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);

@@ -156,3 +156,40 @@ def test_batched_mixed_sizes_match_oracle():
         assert rel_l2(st["mom_k"], ref["p1"]) < 1e-4, i
         assert abs(dH[i] - ref["dH"]) < 1e-3 * max(1.0, abs(ref["dH"])), i
     s.close()
+
+
+@pytest.mark.parametrize("plan", [1, 2])
+@pytest.mark.parametrize("n,box,nb", [s for s in SIZES if s[0] >= 64])
+def test_radix_plans_match_oracle(n, box, nb, plan):
+    """The alternative radix plans of the step, y and force passes: the gradient of
+    set_state (y passes, force pass) and, at 64^3 and 128^3, a trajectory (step
+    pass) against the oracle; a plan's results are reproducible."""
+    mk = plain_mock(n, box, nb, nsub=2)
+    a32, b32 = coefficients32(mk)
+    post = oracle_posterior(mk, a32, b32, workers=8)
+    d32, dk = start_state(mk)
+    f, gk, delta = model.force_k(dk, post.lam_k, post.alpha, post.beta)
+    gk[0, 0, 0] = 0.0
+    finals = []
+    for rep in range(2):
+        s = sampler_for(mk, eps=0.05, nsteps=6, seed=23)
+        for cls in range(3):
+            s.set_plan(cls, plan)
+        assert s.launch_config()[1] == [plan] * 3
+        s.set_coefficients(0, a32, b32)
+        s.set_state(0, d32)
+        st = s.state(0)
+        err = rel_l2(st["grad_k"], gk)
+        print(f"N={n} plan {plan}: gradient rel-L2 {err:.2e}")
+        assert err < 1e-5
+        if n <= 128:
+            before = s.state(0)
+            dH, acc = s.trajectory(0)
+            ref = hmc.trajectory(before["delta_k"].astype(np.complex128), post, 0.05, 6, 23, 0, 0)
+            e_p = rel_l2(s.state(0)["mom_k"], ref["p1"])
+            print(f"N={n} plan {plan}: dH {dH[0]:.6e} oracle {ref['dH']:.6e}, p rel-L2 {e_p:.2e}")
+            assert e_p < 1e-4
+            finals.append((dH[0], s.state(0)["delta_k"]))
+        s.close()
+    if finals:
+        assert finals[0][0] == finals[1][0] and np.array_equal(finals[0][1], finals[1][1])
