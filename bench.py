@@ -221,7 +221,7 @@ def learned_main(args):
                                  log=log)
     ess = learned.ess_study(mk, mu, lv, chains=4, burn=100, sweeps=args.steps, eps0=args.eps,
                             log=log)
-    pl, le = ess["plain"], ess["learned"]
+    pl, le, dg = ess["plain"], ess["learned"], ess["diagonal"]
     value = float(np.median(le["ess_per_s"]))
     out = {
         "metric": "P(k) ESS/s learned-mass vs plain at 256^3, same R-hat",
@@ -241,6 +241,9 @@ def learned_main(args):
         "learned": dict(learned.ess_table(le), eps=le["eps"], acceptance=le["acceptance"],
                         ms_per_sweep=le["ms_per_sweep"],
                         data_dominated=learned.ess_table(le, learned.data_dominated_shells(mk))),
+        "diagonal": dict(learned.ess_table(dg), eps=dg["eps"], acceptance=dg["acceptance"],
+                         ms_per_sweep=dg["ms_per_sweep"],
+                         data_dominated=learned.ess_table(dg, learned.data_dominated_shells(mk))),
         "ratio_median_ess_per_s": value / float(np.median(pl["ess_per_s"])),
         "roofline": {"bound": "mfma", "achieved": fwd_flop / (fwd_ms * 1e-3) / 1e12, "peak": 2500.0,
                      "unit": "TFLOP/s", "frac": fwd_flop / (fwd_ms * 1e-3) / 1e12 / 2500.0,

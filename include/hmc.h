@@ -273,6 +273,15 @@ hmc_status hmc_shell_index(hmc_ctx* ctx, int32_t chain, int16_t* out_dev);
  * HMC_EUNSUPPORTED and do nothing. */
 hmc_status hmc_set_mass(hmc_ctx* ctx, int32_t chain, const float* logvar_dev);
 
+/* The real-space diagonal variant of the mass from the same field: the learned
+ * form above with the Fourier diagonal replaced by the constant m_k = 1/mean(v)
+ * (v = exp(logvar_dev)), so no Fourier preconditioning; its inverse mass is
+ * P diag(v) P less one rank-one term (the mean of the whitened momentum stays
+ * frozen), positive definite on the zero-mean fields.  It runs on the same passes as hmc_set_mass (the
+ * same cost per step).  NULL restores the plain mass; chain = -1 and the rule
+ * on mixed kinds are as for hmc_set_mass (the two learned kinds may be mixed). */
+hmc_status hmc_set_mass_diagonal(hmc_ctx* ctx, int32_t chain, const float* logvar_dev);
+
 /* Graph replay: with enable = 1, leapfrog_trajectory and gibbs_sweep record
  * their device work once into a HIP graph on a library-owned stream (default
  * priority, ordered after and before the caller's stream by events) and replay

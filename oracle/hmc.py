@@ -19,7 +19,7 @@ Readings (the paper leaves these open):
 State variables are delta_hat (half grid) and p_hat; sums over the stored
 half grid carry the full-grid weight w_k (``grid.half_weights``).
 """
-from dataclasses import dataclass
+from dataclasses import dataclass, replace
 
 import numpy as np
 
@@ -157,6 +157,18 @@ def mass_factor(logvar):
     """D^(1/2) with D = v / mean(v), v = exp(logvar)."""
     v = np.exp(np.asarray(logvar, dtype=np.float64))
     return np.sqrt(v / v.mean())
+
+
+def diagonal_mass(post, logvar):
+    """The real-space diagonal variant of the mass from the same field v = exp(logvar),
+    written in the learned form above with D = v/mean(v) and the Fourier diagonal
+    replaced by the constant m_k = 1/mean(v).  As the k = 0 entry of the whitened
+    momentum stays frozen, the inverse mass is P D^(1/2) (I - Pi_0) D^(1/2) P mean(v)
+    (Pi_0 the projection on constant fields): P diag(v) P less one rank-one term,
+    positive definite on the zero-mean fields.  Returns (posterior with that m_k,
+    D^(1/2)) for trajectory_learned."""
+    v = np.exp(np.asarray(logvar, dtype=np.float64))
+    return replace(post, mass_k=np.full_like(post.mass_k, 1.0 / v.mean())), np.sqrt(v / v.mean())
 
 
 def trajectory_learned(dk, post, sqrtD, eps, nsteps, seed, chain, traj):

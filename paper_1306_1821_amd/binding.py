@@ -44,7 +44,7 @@ class HmcSweepStats(ctypes.Structure):
 EXPORTS = ["hmc_workspace_bytes", "hmc_init", "hmc_init_batch", "leapfrog_trajectory",
            "leapfrog_trajectory_async", "gibbs_sweep_async", "hmc_sweep_record_doubles",
            "hamiltonian", "shell_power", "gibbs_sweep", "hmc_set_state", "hmc_set_params",
-           "hmc_set_step", "hmc_warm_start", "hmc_set_launch", "hmc_set_plan", "hmc_get_launch", "hmc_autotune", "hmc_set_coefficients", "hmc_get_params", "hmc_shell_index", "hmc_set_mass",
+           "hmc_set_step", "hmc_warm_start", "hmc_set_launch", "hmc_set_plan", "hmc_get_launch", "hmc_autotune", "hmc_set_coefficients", "hmc_get_params", "hmc_shell_index", "hmc_set_mass", "hmc_set_mass_diagonal",
            "hmc_timing", "hmc_use_graph", "hmc_last_error", "hmc_destroy",
            "cnn_param_count", "cnn_create", "cnn_get_params", "cnn_forward", "cnn_gradient",
            "cnn_features",
@@ -91,6 +91,7 @@ def lib(path=LIB_PATH):
     L.hmc_get_params.argtypes = [P, I32, D, D, D]
     L.hmc_shell_index.argtypes = [P, I32, P]
     L.hmc_set_mass.argtypes = [P, I32, P]
+    L.hmc_set_mass_diagonal.argtypes = [P, I32, P]
     L.hmc_timing.argtypes = [P, I32, D, ctypes.POINTER(ctypes.c_int64)]
     L.hmc_use_graph.argtypes = [P, I32]
     L.hmc_last_error.argtypes = [P]
@@ -296,17 +297,19 @@ class Sampler:
                                                 ctypes.c_void_p(b.data_ptr())))
         self.torch.cuda.synchronize(self.device)
 
-    def set_mass(self, chain, logvar=None):
+    def set_mass(self, chain, logvar=None, kind="learned"):
         """Install the learned mass from a log-variance field (None: plain mass);
-        chain None: every chain."""
+        chain None: every chain.  kind "diagonal": the real-space diagonal variant
+        (inverse mass P diag(exp(logvar)) P, no Fourier preconditioning)."""
         chain = -1 if chain is None else chain
+        fn = {"learned": self.L.hmc_set_mass, "diagonal": self.L.hmc_set_mass_diagonal}[kind]
         if logvar is None:
-            self._check(self.L.hmc_set_mass(self.ctx, chain, None))
+            self._check(fn(self.ctx, chain, None))
             return
         x = logvar if isinstance(logvar, self.torch.Tensor) else \
             self.torch.as_tensor(np.asarray(logvar, dtype=np.float32))
         x = x.to(self.device, dtype=self.torch.float32).contiguous()
-        self._check(self.L.hmc_set_mass(self.ctx, chain, ctypes.c_void_p(x.data_ptr())))
+        self._check(fn(self.ctx, chain, ctypes.c_void_p(x.data_ptr())))
         self.torch.cuda.synchronize(self.device)
 
     def get_params(self, chain=0):

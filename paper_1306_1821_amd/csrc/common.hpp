@@ -70,7 +70,7 @@ struct ChainDev {
   int tb[kTileClasses];   // first global tile of this chain per class
   int nt[kTileClasses];   // tiles of this chain per class
   int maxtiles;           // stride of the partial-sum slots
-  int pad0;
+  int mass_flat;          // 1: real-space diagonal mass (k-space mass 1/mean(v) for every mode)
   // caller buffers
   const float* R;
   const float* counts;

@@ -1817,7 +1817,9 @@ __global__ void k_tables(const ChainDev* __restrict__ ch) {
   const double abar = d.P[kAbar];
   for (int m = threadIdx.x; m < d.nb; m += blockDim.x) {
     const double il = 1.0 / d.P[kLam + m];
-    const double ms = il + abar;
+    // plain mass m_k = 1/lambda + mean(alpha); the real-space diagonal variant
+    // M^-1 = P diag(v) P takes m_k = 1/mean(v) for every mode (with D = v/mean(v))
+    const double ms = d.mass_flat ? 1.0 / d.P[kLmean] : il + abar;
     d.td[kDInvLam + m] = il;
     d.td[kDInvMass + m] = 1.0 / ms;
     d.tf[kTInvLam + m] = (float)il;

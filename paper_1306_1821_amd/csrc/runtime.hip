@@ -1139,9 +1139,10 @@ hmc_status hmc_timing(hmc_ctx* c, int32_t enable, double* ms, int64_t* launches)
   return HMC_OK;
 }
 
-static hmc_status set_mass_one(hmc_ctx* c, Chain& k, const float* logvar_dev) {
+static hmc_status set_mass_one(hmc_ctx* c, Chain& k, const float* logvar_dev, bool flat) {
   if (logvar_dev == nullptr) {
     k.learned = false;
+    k.dev.mass_flat = 0;
     return HMC_OK;
   }
   const int tr = k.dev.nt[kTileR], tz = k.dev.nt[kTileZ], tx = k.dev.nt[kTileXY];
@@ -1157,13 +1158,14 @@ static hmc_status set_mass_one(hmc_ctx* c, Chain& k, const float* logvar_dev) {
   hmc_status st = check_launch(c);
   if (st != HMC_OK) return st;
   k.learned = true;
+  k.dev.mass_flat = flat ? 1 : 0;
   return HMC_OK;
 }
 
-hmc_status hmc_set_mass(hmc_ctx* c, int32_t chain, const float* logvar_dev) {
+static hmc_status set_mass_kind(hmc_ctx* c, int32_t chain, const float* logvar_dev, bool flat) {
   if (!c || chain < -1 || chain >= (int)c->ch.size()) return fail(c, HMC_EINVAL, "bad argument");
   if (chain >= 0) {
-    hmc_status st = set_mass_one(c, c->ch[chain], logvar_dev);
+    hmc_status st = set_mass_one(c, c->ch[chain], logvar_dev, flat);
     if (st != HMC_OK) return st;
   } else {
     for (auto& k : c->ch) {
@@ -1171,10 +1173,15 @@ hmc_status hmc_set_mass(hmc_ctx* c, int32_t chain, const float* logvar_dev) {
         return fail(c, HMC_EINVAL, "chain -1 with a field needs chains of one grid size");
     }
     for (auto& k : c->ch) {
-      hmc_status st = set_mass_one(c, k, logvar_dev);
+      hmc_status st = set_mass_one(c, k, logvar_dev, flat);
       if (st != HMC_OK) return st;
     }
   }
+  // the mass tables follow the kind (and, for the diagonal variant, mean(v))
+  hmc_status st = upload_desc(c);
+  if (st != HMC_OK) return st;
+  launch_tables(c->d_all, (int)c->ch.size(), c->stream);
+  if ((st = check_launch(c)) != HMC_OK) return st;
   bool all = true, any = false;
   for (auto& kk : c->ch) {
     all &= kk.learned;
@@ -1188,6 +1195,14 @@ hmc_status hmc_set_mass(hmc_ctx* c, int32_t chain, const float* logvar_dev) {
   c->g_traj.clear();
   c->g_sweep.clear();
   return HMC_OK;
+}
+
+hmc_status hmc_set_mass(hmc_ctx* c, int32_t chain, const float* logvar_dev) {
+  return set_mass_kind(c, chain, logvar_dev, false);
+}
+
+hmc_status hmc_set_mass_diagonal(hmc_ctx* c, int32_t chain, const float* logvar_dev) {
+  return set_mass_kind(c, chain, logvar_dev, true);
 }
 
 }  // extern "C"

@@ -209,12 +209,13 @@ def warm_up(sampler, trajs, first_index=2 << 30):
 
 
 def start_chains(mk, n_chains, start=None, mu=None, lv=None, mass=None, eps=None, seed=11,
-                 graph=True):
+                 graph=True, mass_kind="learned"):
     """A sampler with n_chains chains on mock mk (chain ids 0..n-1, shared seed).
 
     start: None (delta = 0), "mean" (delta = mu) or "draw" (hmc_warm_start from
     mu and lv, draw index = chain id, so chains start apart); mass: log-variance
-    field of the learned mass for every chain (None: the plain mass)."""
+    field of the learned mass for every chain (None: the plain mass); mass_kind:
+    "learned" or "diagonal" (the real-space diagonal variant)."""
     s = Sampler([chain_from_mock(mk, seed=seed, chain_id=i, **({} if eps is None else dict(eps=eps)))
                  for i in range(n_chains)])
     for i in range(n_chains):
@@ -223,7 +224,7 @@ def start_chains(mk, n_chains, start=None, mu=None, lv=None, mass=None, eps=None
         elif start == "draw":
             s.warm_start(i, mu, lv, draw_index=i)
     if mass is not None:
-        s.set_mass(None, mass)
+        s.set_mass(None, mass, kind=mass_kind)
     s.use_graph(graph)
     return s
 
@@ -293,14 +294,19 @@ def burn_in_study(mk, mu, lv, sweeps=300, warm_trajs=0, eps=(None, None), seed=1
 
 def ess_study(mk, mu, lv, chains=4, burn=100, sweeps=600, target=0.8, eps0=None, seed=21,
               log=None):
-    """P(k) efficiency of the plain and the learned mass: `chains` chains each,
+    """P(k) efficiency of the plain mass, the learned mass and its real-space diagonal
+    variant: `chains` chains each,
     warm-started from (mu, lv) with different draws, step size tuned to the
     same acceptance, `burn` sweeps dropped, then ESS, ESS/s and split R-hat of
     ln P per shell."""
     out = {}
-    for name, mass in [("plain", None), ("learned", lv)]:
-        s = start_chains(mk, chains, "draw", mu, lv, mass, eps0, seed)
-        eps, rate = tune_step(s, eps0 if eps0 is not None else mk["cfg"].eps, target=target)
+    for name, mass, kind in [("plain", None, "learned"), ("learned", lv, "learned"),
+                             ("diagonal", lv, "diagonal")]:
+        s = start_chains(mk, chains, "draw", mu, lv, mass, eps0, seed, mass_kind=kind)
+        # the diagonal variant lacks the Fourier preconditioning: its step can be far
+        # smaller, so it gets more tuning rounds (each moves eps by at most 2x)
+        eps, rate = tune_step(s, eps0 if eps0 is not None else mk["cfg"].eps, target=target,
+                              rounds=10 if kind == "diagonal" else 5)
         for i in range(chains):          # tuning moved the states: start again
             s.warm_start(i, mu, lv, draw_index=i)
         run_chains(s, burn)

@@ -109,3 +109,47 @@ def test_trained_network_shortens_burn_in():
     zero, warm = runs["zero"], runs["warm"]
     assert warm["first_accept"] == 0
     assert warm["burn_pot"] + 10 <= zero["burn_pot"]
+
+
+@pytest.mark.parametrize("case,eps,nsteps", [("small16", 0.05, 8), ("cfg1", 0.03, 10), (64, 0.03, 6)])
+def test_diagonal_mass_trajectory_matches_oracle(case, eps, nsteps):
+    """The real-space diagonal variant of the mass (constant Fourier mass 1/mean(v),
+    D = v / mean(v)) against the oracle; switching to the learned kind and back to
+    the plain mass restores their trajectories."""
+    mk = case_mock(case)
+    n = mk["cfg"].n
+    rng = np.random.default_rng(n + 1)
+    logvar = (0.6 * rng.standard_normal((n, n, n)) - 2.0).astype(np.float32)
+    a32, b32 = coefficients32(mk)
+    s = Sampler([chain_spec(mk, eps=eps, nsteps=nsteps, seed=47)])
+    s.set_coefficients(0, a32, b32)
+    s.set_state(0, start_state(mk)[0])
+    s.set_mass(0, logvar, kind="diagonal")
+    post = oracle_posterior(mk, a32, b32, workers=8)
+    post_d, sqrtD = hmc.diagonal_mass(post, logvar.astype(np.float64))
+    for traj in range(2):
+        before = s.state(0)
+        dH, acc = s.trajectory(traj)
+        st = s.state(0)
+        ref = hmc.trajectory_learned(before["delta_k"].astype(np.complex128), post_d, sqrtD, eps,
+                                     nsteps, 47, 0, traj)
+        e_p = rel_l2(st["mom_k"], ref["p1"])
+        print(f"N={n} diagonal traj {traj}: dH gpu {dH[0]:.6e} oracle {ref['dH']:.6e}; p rel-L2 {e_p:.2e}")
+        assert e_p < 1e-4
+        assert abs(dH[0] - ref["dH"]) < 2e-3 * max(1.0, abs(ref["dH"]))
+        if abs(ref["log_u"] + ref["dH"]) > 1e-2:
+            assert bool(acc[0]) == ref["accepted"]
+        if acc[0]:
+            assert rel_l2(st["delta_k"], ref["proposal"]) < 1e-4
+    s.set_mass(0, logvar)                       # learned kind
+    before = s.state(0)
+    dH, acc = s.trajectory(7)
+    ref = hmc.trajectory_learned(before["delta_k"].astype(np.complex128), post,
+                                 hmc.mass_factor(logvar.astype(np.float64)), eps, nsteps, 47, 0, 7)
+    assert rel_l2(s.state(0)["mom_k"], ref["p1"]) < 1e-4
+    s.set_mass(0, None)                         # plain
+    before = s.state(0)
+    dH, acc = s.trajectory(8)
+    ref = hmc.trajectory(before["delta_k"].astype(np.complex128), post, eps, nsteps, 47, 0, 8)
+    assert rel_l2(s.state(0)["mom_k"], ref["p1"]) < 1e-4
+    s.close()

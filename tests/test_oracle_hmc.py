@@ -205,6 +205,54 @@ def test_learned_mass_reversible_and_second_order():
     assert np.all(np.abs(slopes - 2.0) < 0.15), slopes
 
 
+def test_diagonal_mass_drift_is_p_diag_v_p_minus_rank_one():
+    """Real-space diagonal variant (reading of the mass freedom after eq.
+    Mass_matrix): a real-space momentum r (zero mean) enters as p_hat =
+    F(D^(1/2) r) with its k = 0 entry zeroed (the whitened mean stays frozen), and
+    the drift velocity is the inverse mass applied to r,
+        P diag(v) r - mean(v) (s . r / N^3) P s,   s = D^(1/2) = sqrt(v / mean(v)):
+    P diag(v) P up to one rank-one term, positive on the zero-mean fields.  Checked
+    against that expanded form with numpy's FFT, and the kinetic energy against
+    1/2 mean(v) |s r - mean(s r)|^2."""
+    mk, cfg, post, dk = posterior()
+    n = cfg.n
+    rng = np.random.default_rng(31)
+    lv = 0.7 * rng.standard_normal((n, n, n)) - 1.5
+    post_d, sqrtD = hmc.diagonal_mass(post, lv)
+    v = np.exp(lv)
+    mv = v.mean()
+    r = rng.standard_normal((n, n, n))
+    r -= r.mean()
+    pk = np.fft.rfftn(sqrtD * r, norm="ortho")
+    pk[0, 0, 0] = 0.0
+    got = hmc.learned_velocity(pk, post_d, sqrtD)
+    s = np.sqrt(v / mv)
+    w = v * r
+    y = (w - w.mean()) - mv * np.mean(s * r) * (s - s.mean())
+    want = np.fft.rfftn(y, norm="ortho")
+    assert np.max(np.abs(got - want)) < 1e-12 * np.max(np.abs(want))
+    kin = hmc.energies(dk, pk, grid.inv(dk, n), post_d)[0]
+    q = s * r - np.mean(s * r)
+    assert abs(kin - 0.5 * mv * np.sum(q * q)) < 1e-10 * kin
+
+
+def test_diagonal_mass_reversible_and_second_order():
+    mk, cfg, post, dk = posterior()
+    rng = np.random.default_rng(17)
+    post_d, sqrtD = hmc.diagonal_mass(post, 0.6 * rng.standard_normal((cfg.n,) * 3) - 2.0)
+    p = hmc.draw_momentum(post_d, 5, 0, 0)
+    d1, p1, _ = hmc.leapfrog_learned(dk, p, post_d, sqrtD, 0.05, 10)
+    d2, p2, _ = hmc.leapfrog_learned(d1, -p1, post_d, sqrtD, 0.05, 10)
+    assert np.max(np.abs(d2 - dk)) < 1e-10 * np.max(np.abs(dk))
+    H0 = sum(hmc.energies(dk, p, grid.inv(dk, cfg.n), post_d))
+    errs = []
+    for eps, k in [(0.02, 10), (0.01, 20), (0.005, 40)]:
+        a, b, x = hmc.leapfrog_learned(dk, p, post_d, sqrtD, eps, k)
+        errs.append(abs(sum(hmc.energies(a, b, x, post_d)) - H0))
+    slopes = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(np.abs(slopes - 2.0) < 0.15), (errs, slopes)
+
+
 def _lam_full(post, n, nb):
     sh = dense.shell_full(n, nb)
     lam_m = np.zeros(nb)
