@@ -224,3 +224,15 @@ def test_pass_timing_classes_and_sampling():
         assert np.array_equal(runs[enable][3], runs[0][3])
         for a, b in zip(runs[enable][0], runs[0][0]):
             assert a[0][0] == b[0][0] and a[1][0] == b[1][0]
+
+
+def test_joint_move_shortens_pk_correlation():
+    """Ablation of the joint (P, delta) move at 32^3: with it the median correlation
+    length of ln P over shells is shorter than without (same chains, eps, steps)."""
+    from paper_1306_1821_amd import studies
+    from synth import CONFIGS, make_mock
+    mk = make_mock(CONFIGS["cfg1"], dtype=np.float32)
+    r = studies.joint_move_ablation(mk, chains=4, burn=50, sweeps=1500, lags=(1, 10, 100))
+    j, nj = np.median(r["joint"]["corr_len"]), np.median(r["no_joint"]["corr_len"])
+    print("median correlation length with / without the joint move:", j, nj)
+    assert j < nj
