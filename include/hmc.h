@@ -122,7 +122,8 @@ size_t hmc_workspace_bytes(const hmc_config* cfg);
  * the text after eq. Mass_matrix (diagonal of S^-1 + diag(alpha) in Fourier
  * space), and the real field and gradient of the initial delta_hat (which the
  * caller has written to delta_k; zeros are fine).  bias, nbar: [c] host
- * float64; pk: [n_bins] host float64 (Mpc/h)^3. */
+ * float64; pk: [n_bins] host float64 (Mpc/h)^3.  HMC_EINVAL (after the device
+ * sums) if a k-shell has no modes or a subsample has no voxel with R > 0. */
 hmc_status hmc_init(const hmc_config* cfg, const hmc_buffers* buf, const double* bias,
                     const double* nbar, const double* pk, void* stream, hmc_ctx** out);
 

@@ -177,7 +177,18 @@ template <> struct XC<8>   { static constexpr int T = 2,  B = 128; using RL = Ra
 template <> struct XC<16>  { static constexpr int T = 4,  B = 64;  using RL = Radices<4, 4>; };
 template <> struct XC<32>  { static constexpr int T = 4,  B = 64;  using RL = Radices<8, 4>; };
 template <> struct XC<64>  { static constexpr int T = 8,  B = 32;  using RL = Radices<8, 8>; };
+// 128^3 x/y pencil shape: 16 threads x 16 columns, radices 8.4.4 (520 tiles; the
+// 8 x 32 shape leaves 260 workgroups for 256 compute units: 5 % slower sweeps)
+#ifndef HMC_XCFG128
+#define HMC_XCFG128 1
+#endif
+#if HMC_XCFG128 == 1
+template <> struct XC<128> { static constexpr int T = 16, B = 16;  using RL = Radices<8, 4, 4>; };
+#elif HMC_XCFG128 == 2
+template <> struct XC<128> { static constexpr int T = 32, B = 8;   using RL = Radices<4, 4, 4, 2>; };
+#else
 template <> struct XC<128> { static constexpr int T = 8,  B = 32;  using RL = Radices<16, 8>; };
+#endif
 template <> struct XC<192> { static constexpr int T = 16, B = 16;  using RL = Radices<4, 4, 12>; };
 #if HMC_XCFG256 == 1
 template <> struct XC<256> { static constexpr int T = 32, B = 8;   using RL = Radices<8, 8, 4>; };
@@ -212,8 +223,16 @@ template <int N> constexpr bool has_plans() { return N == 64 || N == 128 || N ==
 template <int N, int P> struct XPlan { using RL = typename XC<N>::RL; };
 template <> struct XPlan<64, 1>  { using RL = Radices<4, 4, 4>; };
 template <> struct XPlan<64, 2>  { using RL = Radices<2, 4, 8>; };
+#if HMC_XCFG128 == 1
+template <> struct XPlan<128, 1> { using RL = Radices<4, 8, 4>; };
+template <> struct XPlan<128, 2> { using RL = Radices<2, 8, 8>; };
+#elif HMC_XCFG128 == 2
+template <> struct XPlan<128, 1> { using RL = Radices<2, 4, 4, 4>; };
+template <> struct XPlan<128, 2> { using RL = Radices<4, 2, 4, 4>; };
+#else
 template <> struct XPlan<128, 1> { using RL = Radices<8, 16>; };
 template <> struct XPlan<128, 2> { using RL = Radices<4, 4, 8>; };
+#endif
 template <> struct XPlan<192, 1> { using RL = Radices<12, 4, 4>; };
 template <> struct XPlan<192, 2> { using RL = Radices<4, 12, 4>; };
 template <> struct XPlan<256, 1> { using RL = Radices<4, 4, 16>; };

@@ -604,6 +604,13 @@ hmc_status hmc_init_batch(const hmc_config* cfg, const hmc_buffers* buf, int32_t
         c->err = "a k-shell has no modes; use fewer bins";
         return bail(HMC_EINVAL);
       }
+  // the Nbar^l conditional needs observed voxels (R^l > 0) in every subsample
+  for (auto& k : c->ch)
+    for (int l = 0; l < k.dev.nsub; ++l)
+      if (k.hp[kNobs + l] <= 0) {
+        c->err = "a subsample has no voxel with R > 0";
+        return bail(HMC_EINVAL);
+      }
   *out = c;
   return HMC_OK;
 }

@@ -16,6 +16,18 @@ structure:
   variance Nbar R, eq. cov_mat_noise).
 
 Voxel centres sit at (i + 1/2) dx - L/2 from the observer at the box centre.
+
+Magnitude-binned surveys (MockConfig.lf, the paper's own test scenario of Sec.
+"Generating artificial observations" with synthetic geometry): subsample l holds
+the galaxies of absolute-magnitude bin [M_l, M_l+1] of [-23, -17]; its radial
+selection f^l(r) is the fraction of the bin's Schechter luminosity function
+(alpha = -1.05, M* - 5 log h = -20.44) visible within 14.5 < r_Petrosian < 17.77
+at the voxel's luminosity distance (flat LCDM, Omega_m = 0.3, low-z Hubble flow
+in h units), R^l = C f^l; the biases follow the luminosity-dependent relation
+b^l = b* (a + b 10^(0.4 (M*_b - M^l)) + c (M^l - M*_b)) with a = 0.895,
+b = 0.105, c = -0.040, M*_b = -20.83, b* = 1.2 at the bin centres M^l; Nbar^l is
+the luminosity function integrated over the bin times the voxel volume, with
+Phi* = 0.0149 h^3 Mpc^-3 (a stated normalisation; the paper leaves it free).
 """
 from dataclasses import dataclass, field
 from typing import List
@@ -41,6 +53,7 @@ class MockConfig:
     eps: float = 0.05
     nsteps: int = 20
     rj: bool = False
+    lf: bool = False   # magnitude-binned subsamples from the Schechter luminosity function
 
     @property
     def nsub(self):
@@ -51,6 +64,78 @@ def _survey(name, n, box, bias, nbar, nb, **kw):
     r_max = 0.7 * box
     return MockConfig(name, n, box, bias, nbar, nb, cap_deg=50.47, r_s=150.0 * r_max / 350.0,
                       rings_deg=[12.6, 25.2, 37.9], n_holes=200, **kw)
+
+
+# --------------------------------------------------------------------------- magnitude bins
+LF_ALPHA, LF_MSTAR, LF_PHISTAR = -1.05, -20.44, 0.0149      # Schechter, r band, h units
+BIAS_A, BIAS_B, BIAS_C, BIAS_MSTAR, BIAS_BSTAR = 0.895, 0.105, -0.040, -20.83, 1.2
+M_BRIGHT, M_FAINT, R_BRIGHT, R_FAINT = -23.0, -17.0, 14.5, 17.77
+OMEGA_M = 0.3
+
+
+def schechter(M):
+    """Phi(M) per unit magnitude (h^3 Mpc^-3) of the Schechter form (appendix)."""
+    x = 10.0 ** (0.4 * (LF_MSTAR - np.asarray(M, dtype=np.float64)))
+    return 0.4 * np.log(10.0) * LF_PHISTAR * x ** (LF_ALPHA + 1.0) * np.exp(-x)
+
+
+def _lf_integral(lo, hi, pts=2001):
+    """int_lo^hi Phi(M) dM (elementwise over arrays lo <= hi), composite Simpson."""
+    lo, hi = np.broadcast_arrays(np.asarray(lo, np.float64), np.asarray(hi, np.float64))
+    t = np.linspace(0.0, 1.0, pts)
+    w = np.ones(pts)
+    w[1:-1:2], w[2:-1:2] = 4.0, 2.0
+    M = lo[..., None] + (hi - lo)[..., None] * t
+    return (hi - lo) * (schechter(M) @ w) / (3.0 * (pts - 1))
+
+
+def magnitude_bins(nsub):
+    edges = np.linspace(M_BRIGHT, M_FAINT, nsub + 1)
+    return edges, 0.5 * (edges[:-1] + edges[1:])
+
+
+def lf_bias(M):
+    """Luminosity-dependent bias at absolute magnitude M."""
+    M = np.asarray(M, dtype=np.float64)
+    return BIAS_BSTAR * (BIAS_A + BIAS_B * 10.0 ** (0.4 * (BIAS_MSTAR - M)) + BIAS_C * (M - BIAS_MSTAR))
+
+
+def distance_modulus(r):
+    """m - (M - 5 log h) at comoving distance r (Mpc/h): 5 log10 D_L + 25, D_L = (1 + z) r,
+    z(r) from flat LCDM with Omega_m = OMEGA_M."""
+    z = np.linspace(0.0, 1.0, 4001)
+    ez = np.sqrt(OMEGA_M * (1.0 + z) ** 3 + 1.0 - OMEGA_M)
+    chi = np.concatenate([[0.0], np.cumsum(0.5 * (1.0 / ez[1:] + 1.0 / ez[:-1]) * np.diff(z))])
+    chi *= 299792.458 / 100.0
+    zr = np.interp(np.asarray(r, np.float64), chi, z)
+    return 5.0 * np.log10(np.maximum((1.0 + zr) * np.asarray(r, np.float64), 1e-6)) + 25.0
+
+
+def lf_selection(r, nsub, table=8192):
+    """f^l(r) for the nsub magnitude bins: [nsub] + r.shape (evaluated on a table of
+    `table` radii up to max r, then linearly interpolated per voxel)."""
+    edges, _ = magnitude_bins(nsub)
+    r = np.asarray(r, np.float64)
+    rt = np.linspace(0.0, float(r.max()) * 1.0001 + 1e-9, table)
+    dm = distance_modulus(rt)
+    m_lo, m_hi = R_BRIGHT - dm, R_FAINT - dm                 # visible absolute magnitudes
+    out = np.empty((nsub,) + r.shape)
+    for l in range(nsub):
+        lo = np.clip(m_lo, edges[l], edges[l + 1])
+        hi = np.clip(m_hi, edges[l], edges[l + 1])
+        ft = _lf_integral(lo, hi, pts=401) / _lf_integral(edges[l], edges[l + 1])
+        out[l] = np.interp(r, rt, ft)
+    return out
+
+
+def _lf_survey(name, n, box, nsub, nb, **kw):
+    """The paper's magnitude-binned scenario on synthetic geometry."""
+    _, mc = magnitude_bins(nsub)
+    edges, _ = magnitude_bins(nsub)
+    nbar = [float(_lf_integral(edges[l], edges[l + 1]) * (box / n) ** 3) for l in range(nsub)]
+    cfg = _survey(name, n, box, [float(b) for b in lf_bias(mc)], nbar, nb, **kw)
+    cfg.lf = True
+    return cfg
 
 
 CONFIGS = {
@@ -75,6 +160,13 @@ CONFIGS = {
                       mask_seed=1, nsteps=30),
     "grp192": _survey("grp192", 192, 1500.0, [1.0, 1.2, 1.4], [5.0, 2.0, 1.0], 60,
                       mask_seed=2, nsteps=30),
+    # the paper's scenario: 15 magnitude bins in [-23, -17], 128^3 at L = 750 Mpc/h
+    "paper15": _lf_survey("paper15", 128, 750.0, 15, 40, nsteps=30, eps=0.05, rj=True,
+                          mask_seed=3),
+    # the same scenario at 64^3 (L = 375 Mpc/h, the same voxel size) for parity tests:
+    # the smallest box whose survey cone reaches the brightest bin (r > ~250 Mpc/h)
+    "paper15s": _lf_survey("paper15s", 64, 375.0, 15, 20, nsteps=20, eps=0.05, rj=True,
+                           mask_seed=3),
 }
 
 
@@ -178,13 +270,19 @@ def make_mock(cfg, dtype=np.float64, geometry=None):
     obs = R1 > 0
     rng = np.random.default_rng(2000 + cfg.seed)
     c = cfg.nsub
+    if cfg.lf:
+        sel_l = lf_selection(_directions(n, box)[3], c)
     R = np.empty((c, n, n, n), dtype=dtype)
     counts = np.empty((c, n, n, n), dtype=dtype)
     for l in range(c):
         eps = rng.standard_normal((n, n, n))
-        mu = cfg.nbar[l] * R1 * (1.0 + cfg.bias[l] * delta)
-        counts[l] = np.where(obs, mu + np.sqrt(cfg.nbar[l] * R1) * eps, 0.0)
-        R[l] = R1
+        Rl = C * sel_l[l] if cfg.lf else R1
+        ob = Rl > 0
+        mu = cfg.nbar[l] * Rl * (1.0 + cfg.bias[l] * delta)
+        counts[l] = np.where(ob, mu + np.sqrt(cfg.nbar[l] * Rl) * eps, 0.0)
+        R[l] = Rl
+        if cfg.lf:
+            obs = obs | ob
     pk_init = A * fiducial_shape(shell_centres(n, box, cfg.nb))
     return dict(cfg=cfg, R=R, counts=counts, delta=delta, pk_init=pk_init, A=A,
                 mask=C.astype(dtype), sel=sel.astype(dtype),

@@ -25,7 +25,8 @@ def oracle_cfg(mk, spec):
 
 CASES = [("tiny8x2", False, 0.1, 8), ("small16", False, 0.08, 10), ("small16", True, 0.08, 10),
          ("cfg1", False, 0.05, 20), ("cfg1", True, 0.05, 20), (64, True, 0.04, 10),
-         ("small16", "tau", 0.08, 12)]     # drawn step counts, joint move on
+         ("small16", "tau", 0.08, 12),     # drawn step counts, joint move on
+         ("paper15s", True, 0.04, 10)]     # 15 magnitude-binned subsamples, each with its own R
 
 
 def case_mock(name):
