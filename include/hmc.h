@@ -274,6 +274,17 @@ hmc_status hmc_shell_index(hmc_ctx* ctx, int32_t chain, int16_t* out_dev);
  * HMC_EUNSUPPORTED and do nothing. */
 hmc_status hmc_set_mass(hmc_ctx* ctx, int32_t chain, const float* logvar_dev);
 
+/* Posterior field moments (streaming): fold the chain's current real-space
+ * state delta_r into per-voxel running moments with Welford's update in float64:
+ * mean_dev, m2_dev (device [N][N][N] float64, caller-owned) hold the mean and the
+ * sum of squared deviations of the first count - 1 states; count >= 1 is the
+ * number of states including this one (count = 1 starts them: mean = delta,
+ * m2 = 0).  The variance is m2 / (count - 1).  Stream-ordered, no
+ * synchronisation; call after a sweep or trajectory.  HMC_EINVAL on a bad
+ * argument. */
+hmc_status hmc_field_moments(hmc_ctx* ctx, int32_t chain, double* mean_dev, double* m2_dev,
+                             int64_t count);
+
 /* The real-space diagonal variant of the mass from the same field: the learned
  * form above with the Fourier diagonal replaced by the constant m_k = 1/mean(v)
  * (v = exp(logvar_dev)), so no Fourier preconditioning; its inverse mass is

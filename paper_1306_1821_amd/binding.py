@@ -44,7 +44,7 @@ class HmcSweepStats(ctypes.Structure):
 EXPORTS = ["hmc_workspace_bytes", "hmc_init", "hmc_init_batch", "leapfrog_trajectory",
            "leapfrog_trajectory_async", "gibbs_sweep_async", "hmc_sweep_record_doubles",
            "hamiltonian", "shell_power", "gibbs_sweep", "hmc_set_state", "hmc_set_params",
-           "hmc_set_step", "hmc_warm_start", "hmc_set_launch", "hmc_set_plan", "hmc_get_launch", "hmc_autotune", "hmc_set_coefficients", "hmc_get_params", "hmc_shell_index", "hmc_set_mass", "hmc_set_mass_diagonal",
+           "hmc_set_step", "hmc_warm_start", "hmc_set_launch", "hmc_set_plan", "hmc_get_launch", "hmc_autotune", "hmc_set_coefficients", "hmc_get_params", "hmc_shell_index", "hmc_set_mass", "hmc_set_mass_diagonal", "hmc_field_moments",
            "hmc_timing", "hmc_use_graph", "hmc_last_error", "hmc_destroy",
            "cnn_param_count", "cnn_create", "cnn_get_params", "cnn_forward", "cnn_gradient",
            "cnn_features",
@@ -92,6 +92,7 @@ def lib(path=LIB_PATH):
     L.hmc_shell_index.argtypes = [P, I32, P]
     L.hmc_set_mass.argtypes = [P, I32, P]
     L.hmc_set_mass_diagonal.argtypes = [P, I32, P]
+    L.hmc_field_moments.argtypes = [P, I32, P, P, ctypes.c_int64]
     L.hmc_timing.argtypes = [P, I32, D, ctypes.POINTER(ctypes.c_int64)]
     L.hmc_use_graph.argtypes = [P, I32]
     L.hmc_last_error.argtypes = [P]
@@ -270,6 +271,14 @@ class Sampler:
         x = x.to(self.device, dtype=self.torch.float32).contiguous()
         self._check(self.L.hmc_set_state(self.ctx, chain, ctypes.c_void_p(x.data_ptr())))
         self.torch.cuda.synchronize(self.device)
+
+    def field_moments(self, chain, mean, m2, count):
+        """Fold the chain's current delta_r into running float64 moments (device
+        tensors [N][N][N]); count = number of states including this one."""
+        for t in (mean, m2):
+            assert t.dtype == self.torch.float64 and t.is_contiguous() and t.device == self.device
+        self._check(self.L.hmc_field_moments(self.ctx, int(chain), ctypes.c_void_p(mean.data_ptr()),
+                                             ctypes.c_void_p(m2.data_ptr()), int(count)))
 
     def warm_start(self, chain, mu, logvar, draw_index=0):
         """delta = mu + sqrt(exp(logvar) / sigma^2) x (prior draw x); see hmc_warm_start."""

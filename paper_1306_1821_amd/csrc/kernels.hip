@@ -2071,6 +2071,33 @@ void launch_export(const ChainDev* ch, int nch, int sweep, double* rec, int32_t*
                    hipStream_t s) {
   hipLaunchKernelGGL(k_export, dim3(nch), dim3(128), 0, s, ch, nch, sweep, rec, acc);
 }
+// Running per-voxel mean and sum of squared deviations of a float field over
+// `count` samples (Welford's update, float64 accumulators); count = 1 starts them.
+__global__ void __launch_bounds__(kThreads) k_field_moments(const float* __restrict__ x,
+                                                            double* __restrict__ mean,
+                                                            double* __restrict__ m2, long long nv,
+                                                            long long count) {
+  const double inv = 1.0 / (double)count;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += stride) {
+    const double v = (double)x[i];
+    if (count == 1) {
+      mean[i] = v;
+      m2[i] = 0.0;
+    } else {
+      const double d = v - mean[i];
+      const double mn = mean[i] + d * inv;
+      mean[i] = mn;
+      m2[i] += d * (v - mn);
+    }
+  }
+}
+void launch_field_moments(const float* x, double* mean, double* m2, long long nv, long long count,
+                          hipStream_t s) {
+  const long long blocks = (nv + kThreads - 1) / kThreads;
+  hipLaunchKernelGGL(k_field_moments, dim3((unsigned)(blocks < 8192 ? blocks : 8192)), dim3(kThreads),
+                     0, s, x, mean, m2, nv, count);
+}
 void launch_warm_combine(const ChainDev* ch, int total_r, const float* mu, const float* logvar,
                          hipStream_t s) {
   hipLaunchKernelGGL(k_warm_combine, dim3(eg(total_r)), dim3(kThreads), 0, s, ch, total_r, mu,

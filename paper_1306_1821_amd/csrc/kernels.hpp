@@ -67,6 +67,8 @@ void launch_zpass(int mode, const ChainDev* ch, int nch, int total, int lds, ZAr
 void launch_export(const ChainDev* ch, int nch, int sweep, double* rec, int32_t* acc,
                    hipStream_t s);
 void launch_shell_lut(const ChainDev* ch, int n, hipStream_t s);
+void launch_field_moments(const float* x, double* mean, double* m2, long long nv, long long count,
+                          hipStream_t s);
 void launch_warm_combine(const ChainDev* ch, int total_r, const float* mu, const float* logvar,
                          hipStream_t s);
 

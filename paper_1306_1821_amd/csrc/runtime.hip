@@ -876,6 +876,15 @@ hmc_status hmc_set_state(hmc_ctx* c, int32_t chain, const float* delta_r_dev) {
   return check_launch(c);
 }
 
+hmc_status hmc_field_moments(hmc_ctx* c, int32_t chain, double* mean_dev, double* m2_dev,
+                             int64_t count) {
+  if (!c || !mean_dev || !m2_dev || chain < 0 || chain >= (int)c->ch.size() || count < 1)
+    return fail(c, HMC_EINVAL, "bad argument");
+  Chain& k = c->ch[chain];
+  launch_field_moments(k.buf.delta_r, mean_dev, m2_dev, k.dev.nv, (long long)count, c->stream);
+  return check_launch(c);
+}
+
 hmc_status hmc_warm_start(hmc_ctx* c, int32_t chain, const float* mu_dev,
                           const float* logvar_dev, uint64_t draw_index) {
   if (!c || !mu_dev || !logvar_dev || chain < 0 || chain >= (int)c->ch.size())

@@ -51,3 +51,83 @@ def joint_move_ablation(mk, chains=4, burn=100, sweeps=3000, lags=(1, 10, 100, 1
                 f"data-dominated shells: correlation length {np.median(corr_len[dd]):.0f}, "
                 f"ESS/s {np.median(out[name]['ess_per_s'][dd]):.3g}")
     return out
+
+
+def _corr(a, b):
+    a = np.asarray(a, np.float64) - np.mean(a)
+    b = np.asarray(b, np.float64) - np.mean(b)
+    d = np.sqrt(np.sum(a * a) * np.sum(b * b))
+    return float(np.sum(a * b) / d) if d > 0 else 0.0
+
+
+def posterior_analysis(mk, chains=4, burn=100, sweeps=2000, seed=41, log=None):
+    """Posterior structure of the block sampler on survey `mk` (Sec. "Results": the
+    P-P correlation matrix, the bias-P and Nbar-P correlations, the ensemble mean
+    and credible bands of P(k), mean and standard-deviation maps of the density):
+    chains start at the truth field; after `burn` sweeps every sweep's P, b, Nbar
+    are kept and every chain's density is folded into per-voxel running moments on
+    the device (hmc_field_moments, pooled over chains)."""
+    import torch
+    cfg = mk["cfg"]
+    n, nb, c = cfg.n, cfg.nb, cfg.nsub
+    s = Sampler([chain_from_mock(mk, seed=seed, chain_id=i) for i in range(chains)])
+    for i in range(chains):
+        s.set_state(i, mk["delta"])
+    sig, nmodes = s.shell_power(0)                       # the truth field's shell power
+    p_truth = sig / np.maximum(nmodes, 1) * cfg.box ** 3 / n ** 3
+    s.use_graph(True)
+    run_chains(s, burn)
+    dev = s.device
+    mean = torch.zeros((n, n, n), dtype=torch.float64, device=dev)
+    m2 = torch.zeros_like(mean)
+    pk = np.zeros((chains, sweeps, nb))
+    bias = np.zeros((chains, sweeps, c))
+    nbar = np.zeros((chains, sweeps, c))
+    count = 0
+    for j in range(sweeps):
+        st = s.sweep(burn + j)
+        for i in range(chains):
+            pk[i, j], bias[i, j], nbar[i, j] = st[i]["pk"], st[i]["bias"], st[i]["nbar"]
+            count += 1
+            s.field_moments(i, mean, m2, count)
+    torch.cuda.synchronize(dev)
+    mean_np = mean.cpu().numpy()
+    sd_np = np.sqrt(m2.cpu().numpy() / max(1, count - 1))
+    s.close()
+    lp = np.log(pk).reshape(-1, nb)
+    cpp = np.corrcoef(lp.T)
+    off = cpp[~np.eye(nb, dtype=bool)]
+    adj = np.array([cpp[m, m + 1] for m in range(nb - 1)])
+    free = [l for l in range(c) if not ((cfg.fixed_mask >> l) & 1)]
+    b_flat, nb_flat = bias.reshape(-1, c), nbar.reshape(-1, c)
+    corr_bp = np.array([[_corr(b_flat[:, l], lp[:, m]) for m in range(nb)] for l in free])
+    corr_np = np.array([[_corr(nb_flat[:, l], lp[:, m]) for m in range(nb)] for l in range(c)])
+    corr_bn = np.array([_corr(b_flat[:, l], nb_flat[:, l]) for l in free])
+    lo, med, hi = np.percentile(pk.reshape(-1, nb), [16, 50, 84], axis=0)
+    covered = (lo <= p_truth) & (p_truth <= hi)
+    obs = np.any(np.asarray(mk["R"]) > 0, axis=0)
+    truth = np.asarray(mk["delta"], np.float64)
+    out = dict(
+        sweeps=sweeps, chains=chains,
+        pp_max_abs_offdiag=float(np.max(np.abs(off))), pp_mean_abs_offdiag=float(np.mean(np.abs(off))),
+        pp_adjacent_mean=float(np.mean(adj)),
+        bias_p_corr_median=[float(np.median(r)) for r in corr_bp],
+        nbar_p_corr_median=[float(np.median(r)) for r in corr_np],
+        bias_nbar_corr=[float(x) for x in corr_bn],
+        pk_mean=pk.reshape(-1, nb).mean(axis=0).tolist(), pk_band_16_84=[lo.tolist(), hi.tolist()],
+        pk_truth=p_truth.tolist(), band_covers_truth=float(covered.mean()),
+        mean_map_corr_observed=_corr(mean_np[obs], truth[obs]),
+        mean_map_corr_unobserved=_corr(mean_np[~obs], truth[~obs]) if (~obs).any() else None,
+        sd_map_mean_observed=float(sd_np[obs].mean()),
+        sd_map_mean_unobserved=float(sd_np[~obs].mean()) if (~obs).any() else None,
+        observed_fraction=float(obs.mean()))
+    if log:
+        log(f"P-P correlation: max |off-diagonal| {out['pp_max_abs_offdiag']:.3f}, mean "
+            f"{out['pp_mean_abs_offdiag']:.3f}, adjacent shells {out['pp_adjacent_mean']:.3f}; "
+            f"b-P median per free subsample {np.round(out['bias_p_corr_median'], 3)}; "
+            f"Nbar-P {np.round(out['nbar_p_corr_median'], 3)}; b-Nbar {np.round(out['bias_nbar_corr'], 3)}; "
+            f"68% band covers the truth shell power in {100 * out['band_covers_truth']:.0f}% of shells; "
+            f"mean map vs truth: r = {out['mean_map_corr_observed']:.3f} observed, "
+            f"{out['mean_map_corr_unobserved']} unobserved; sd map mean "
+            f"{out['sd_map_mean_observed']:.3f} observed, {out['sd_map_mean_unobserved']} unobserved")
+    return out

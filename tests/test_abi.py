@@ -84,6 +84,7 @@ def test_null_arguments(L):
     assert L.hmc_set_step(None, 0, 0.1) != binding.HMC_OK
     assert L.hmc_set_plan(None, 0, 0) != binding.HMC_OK
     assert L.hmc_set_mass_diagonal(None, 0, None) != binding.HMC_OK
+    assert L.hmc_field_moments(None, 0, None, None, 1) != binding.HMC_OK
     assert L.hmc_get_launch(None, None, None) != binding.HMC_OK
     L.hmc_destroy(None)
     L.cnn_destroy(None)

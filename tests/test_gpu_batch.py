@@ -236,3 +236,31 @@ def test_joint_move_shortens_pk_correlation():
     j, nj = np.median(r["joint"]["corr_len"]), np.median(r["no_joint"]["corr_len"])
     print("median correlation length with / without the joint move:", j, nj)
     assert j < nj
+
+
+def test_field_moments_match_numpy():
+    """hmc_field_moments: the running float64 mean and sum of squared deviations of
+    delta_r over sweeps of two chains (pooled) equal numpy's on the stored states."""
+    mks = [mock("small16"), mock("small16")]
+    s = Sampler([chain_spec(m, eps=0.08, nsteps=8, seed=61, chain_id=i, rj=True)
+                 for i, m in enumerate(mks)])
+    for i, m in enumerate(mks):
+        s.set_state(i, start_state(m)[0])
+    n = mks[0]["cfg"].n
+    mean = torch.zeros((n, n, n), dtype=torch.float64, device=s.device)
+    m2 = torch.zeros_like(mean)
+    states, count = [], 0
+    for sw in range(6):
+        s.sweep(sw)
+        for i in range(2):
+            count += 1
+            s.field_moments(i, mean, m2, count)
+            states.append(s.state(i)["delta_r"].astype(np.float64))
+    x = np.array(states)
+    mu = x.mean(axis=0)
+    var = x.var(axis=0, ddof=1)
+    assert np.max(np.abs(mean.cpu().numpy() - mu)) < 1e-12 * np.max(np.abs(mu))
+    assert np.max(np.abs(m2.cpu().numpy() / (count - 1) - var)) < 1e-10 * np.max(var)
+    with pytest.raises(Exception):
+        s.field_moments(0, mean, m2, 0)
+    s.close()
