@@ -99,6 +99,9 @@ typedef struct hmc_buffers {
   float* beta;          /* [N][N][N] sum_l b_l (N^l - Nbar_l R^l) (library writes) */
   void* work;           /* workspace, at least hmc_workspace_bytes(cfg) bytes */
   size_t work_bytes;
+  const float* growth;  /* [N][N][N] linear growth factor D+ per voxel of the data model
+                           (eq. data_model: mean counts Nbar R (1 + b D+ delta)), or NULL
+                           for D+ = 1 (the paper's experiments) */
 } hmc_buffers;
 
 /* Per-sweep results; the arrays are library-owned views valid until the next

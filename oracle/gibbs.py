@@ -192,7 +192,8 @@ def sweep(state, data, cfg, s):
     n, box, nb = cfg["n"], cfg["box"], cfg["nb"]
     R, counts = data["R"], data["counts"]
     dk, pk, bias, nbar = state["dk"], state["pk"], state["bias"], state["nbar"]
-    post = hmc.make_posterior(n, box, nb, pk, R, counts, bias, nbar, cfg.get("workers", 1))
+    growth = data.get("growth")                 # per-voxel D+ (eq. data_model), or None
+    post = hmc.make_posterior(n, box, nb, pk, R, counts, bias, nbar, cfg.get("workers", 1), growth)
     if cfg.get("tau_mode", False):
         cfg = dict(cfg, nsteps=hmc.draw_steps(cfg["nsteps"], cfg["seed"],
                                               cfg.get("tau_chain", cfg["chain"]), s))
@@ -209,7 +210,7 @@ def sweep(state, data, cfg, s):
         out.update(rj_dH=jm["dH"], rj_accepted=jm["accepted"])
     delta = grid.inv(dk, n)
     stat = static_moments(R, counts)
-    mom = delta_moments(delta, R, counts)
+    mom = delta_moments(delta if growth is None else np.asarray(growth, np.float64) * delta, R, counts)
     nbar = draw_nbar(stat, mom, bias, cfg["seed"], cfg["chain"], s)
     bias = draw_bias(mom, nbar, bias, cfg["fixed_mask"], cfg["seed"], cfg["chain"], s)
     out.update(dk=dk, pk=lam * box ** 3 / n ** 3, bias=bias, nbar=nbar)

@@ -42,9 +42,9 @@ class Posterior:
     workers: int = 1
 
 
-def make_posterior(n, box, nb, pk, R, counts, bias, nbar, workers=1):
+def make_posterior(n, box, nb, pk, R, counts, bias, nbar, workers=1, growth=None):
     shells = grid.half_shells(n, nb)
-    alpha, beta, abar = model.coefficients(R, counts, bias, nbar)
+    alpha, beta, abar = model.coefficients(R, counts, bias, nbar, growth)
     lam = model.lambdas(pk, n, box)
     return Posterior(n, box, nb, shells, grid.half_weights(n), model.per_mode(lam, shells),
                      model.per_mode(model.mass_table(lam, abar), shells), alpha, beta, abar,

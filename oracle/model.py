@@ -29,8 +29,10 @@ import numpy as np
 from . import grid
 
 
-def coefficients(R, counts, bias, nbar):
-    """alpha, beta of the force (float64 [N][N][N]) and the mean of alpha."""
+def coefficients(R, counts, bias, nbar, growth=None):
+    """alpha, beta of the force (float64 [N][N][N]) and the mean of alpha.  growth:
+    per-voxel linear growth factor D+ of eq. data_model (None: D+ = 1); the mean
+    counts are Nbar R (1 + b D+ delta), so alpha carries D+^2 and beta D+."""
     R = np.asarray(R, dtype=np.float64)
     counts = np.asarray(counts, dtype=np.float64)
     alpha = np.zeros(R.shape[1:])
@@ -39,6 +41,10 @@ def coefficients(R, counts, bias, nbar):
         obs = R[l] > 0
         alpha += np.where(obs, bias[l] ** 2 * nbar[l] * R[l], 0.0)
         beta += np.where(obs, bias[l] * (counts[l] - nbar[l] * R[l]), 0.0)
+    if growth is not None:
+        g = np.asarray(growth, dtype=np.float64)
+        alpha *= g * g
+        beta *= g
     return alpha, beta, float(alpha.mean())
 
 

@@ -30,7 +30,7 @@ class HmcBuffers(ctypes.Structure):
                 ("mom_k", ctypes.c_void_p), ("grad_k", ctypes.c_void_p),
                 ("delta_r", ctypes.c_void_p), ("alpha", ctypes.c_void_p),
                 ("beta", ctypes.c_void_p), ("work", ctypes.c_void_p),
-                ("work_bytes", ctypes.c_size_t)]
+                ("work_bytes", ctypes.c_size_t), ("growth", ctypes.c_void_p)]
 
 
 class HmcSweepStats(ctypes.Structure):
@@ -178,6 +178,8 @@ class Sampler:
                 alpha=torch.zeros((n, n, n), **f32),
                 beta=torch.zeros((n, n, n), **f32),
                 work=torch.zeros(wb, dtype=torch.uint8, device=self.device))
+            if c.get("growth") is not None:
+                t["growth"] = torch.as_tensor(np.asarray(c["growth"], dtype=np.float32)).to(self.device).contiguous()
             if c.get("delta_k0") is not None:
                 t["delta_k"].copy_(torch.as_tensor(np.asarray(c["delta_k0"], dtype=np.complex64)))
             b = bufs[i]
@@ -186,6 +188,7 @@ class Sampler:
                                            t["grad_k"].data_ptr())
             b.delta_r, b.alpha, b.beta = t["delta_r"].data_ptr(), t["alpha"].data_ptr(), t["beta"].data_ptr()
             b.work, b.work_bytes = t["work"].data_ptr(), wb
+            b.growth = t["growth"].data_ptr() if "growth" in t else None
             bias += list(np.asarray(c["bias"], dtype=np.float64))
             nbar += list(np.asarray(c["nbar"], dtype=np.float64))
             pk += list(np.asarray(c["pk"], dtype=np.float64))

@@ -74,6 +74,7 @@ struct ChainDev {
   // caller buffers
   const float* R;
   const float* counts;
+  const float* growth;  // per-voxel growth factor D+, or null (D+ = 1)
   float2* dk;
   float2* pk;
   float2* gk;

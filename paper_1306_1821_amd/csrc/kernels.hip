@@ -1531,6 +1531,14 @@ __global__ void __launch_bounds__(kThreads) k_coeff(const ChainDev* __restrict__
           }
         }
       }
+      if (d.growth) {  // per-voxel growth factor: b -> b D+ in the data model
+        const f4v g = gld4(d.growth, i4);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          al[q] *= g[q] * g[q];
+          be[q] *= g[q];
+        }
+      }
       gst4(d.alpha, i4, al);
       gst4(d.beta, i4, be);
       acc += (double)al[0] + (double)al[1] + (double)al[2] + (double)al[3];
@@ -1610,10 +1618,11 @@ __global__ void __launch_bounds__(kThreads) k_moments(const ChainDev* __restrict
         const f4v r = gld4(d.R + (size_t)l * d.nv, i4);
         const f4v c = gld4(d.counts + (size_t)l * d.nv, i4);
         const f4v x = gld4(d.dr, i4);
+        const f4v g = d.growth ? gld4(d.growth, i4) : f4v{1.f, 1.f, 1.f, 1.f};
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           if (r[q] > 0.f) {
-            const double xq = x[q];
+            const double xq = (double)x[q] * (double)g[q];  // D+ delta
             s1 += (double)r[q] * xq;
             s2 += (double)r[q] * xq * xq;
             st += (double)c[q] * xq;

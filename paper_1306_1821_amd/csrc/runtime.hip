@@ -505,6 +505,7 @@ hmc_status hmc_init_batch(const hmc_config* cfg, const hmc_buffers* buf, int32_t
     d.draw = c->d_draw;
     d.R = k.buf.R;
     d.counts = k.buf.counts;
+    d.growth = k.buf.growth;
     d.dk = (float2*)k.buf.delta_k;
     d.pk = (float2*)k.buf.mom_k;
     d.gk = (float2*)k.buf.grad_k;

@@ -18,7 +18,7 @@ def oracle_cfg(mk, spec):
     cfg = mk["cfg"]
     lam = model.lambdas(mk["pk_init"], cfg.n, cfg.box)
     return dict(n=cfg.n, box=cfg.box, nb=cfg.nb, eps=spec["eps"], nsteps=spec["nsteps"],
-                alpha_prior=1.0, seed=spec["seed"], chain=spec.get("chain_id", 0),
+                alpha_prior=spec.get("alpha_prior", 1.0), seed=spec["seed"], chain=spec.get("chain_id", 0),
                 fixed_mask=spec["fixed_mask"], rj=spec["rj"], lam_lo=lam * np.exp(-10.0),
                 lam_hi=lam * np.exp(10.0), workers=4)
 
@@ -35,15 +35,40 @@ def case_mock(name):
 
 @pytest.mark.parametrize("name,rj,eps,nsteps", CASES)
 def test_sweeps_match_oracle(name, rj, eps, nsteps):
+    run_sweeps(name, rj, eps, nsteps)
+
+
+@pytest.mark.parametrize("rj", [False, True])
+def test_flat_power_prior_sweeps_match_oracle(rj):
+    """The flat prior on P (power-law index alpha = 0, a variant the paper allows)
+    in the P draw and the joint move."""
+    run_sweeps("cfg1", rj, 0.05, 20, alpha_prior=0.0)
+
+
+@pytest.mark.parametrize("rj", [False, True])
+def test_growth_factor_sweeps_match_oracle(rj):
+    """A per-voxel growth factor D+ in the data model (a variant the paper allows):
+    coefficients and the Nbar, b conditionals use D+ delta."""
+    mk = case_mock("cfg1")
+    n, box = mk["cfg"].n, mk["cfg"].box
+    c = (np.arange(n) + 0.5) * box / n - 0.5 * box
+    r = np.sqrt(c[:, None, None] ** 2 + c[None, :, None] ** 2 + c[None, None, :] ** 2)
+    g = (1.0 / (1.0 + r / 400.0)).astype(np.float32)
+    run_sweeps("cfg1", rj, 0.05, 20, growth=g)
+
+
+def run_sweeps(name, rj, eps, nsteps, alpha_prior=1.0, growth=None):
     mk = case_mock(name)
     tau = rj == "tau"
     rj = bool(rj)
-    spec = chain_spec(mk, eps=eps, nsteps=nsteps, seed=23, rj=rj, fixed_mask=1, tau_mode=tau)
+    spec = chain_spec(mk, eps=eps, nsteps=nsteps, seed=23, rj=rj, fixed_mask=1, tau_mode=tau,
+                      alpha_prior=alpha_prior, growth=growth)
     s = Sampler([spec])
     d32, dk = start_state(mk)
     s.set_state(0, d32)
     ocfg = dict(oracle_cfg(mk, spec), tau_mode=tau)
-    data = dict(R=mk["R"].astype(np.float64), counts=mk["counts"].astype(np.float64))
+    data = dict(R=mk["R"].astype(np.float64), counts=mk["counts"].astype(np.float64),
+                growth=None if growth is None else growth.astype(np.float64))
     state = dict(dk=dk, pk=mk["pk_init"].copy(), bias=mk["bias"].copy(), nbar=mk["nbar"].copy())
     for sw in range(5 if tau else 3):
         g = s.sweep(sw)[0]

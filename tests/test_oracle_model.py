@@ -76,3 +76,54 @@ def test_mass_is_fourier_diagonal_of_precision():
     want = model.mass_table(lam_m, abar)[np.maximum(sh, 0)]
     sel = sh >= 0
     assert np.allclose(diag[sel], want[sel], rtol=1e-10)
+
+
+def _growth(mk):
+    n, box = mk["cfg"].n, mk["cfg"].box
+    c = (np.arange(n) + 0.5) * box / n - 0.5 * box
+    r = np.sqrt(c[:, None, None] ** 2 + c[None, :, None] ** 2 + c[None, None, :] ** 2)
+    return 1.0 / (1.0 + r / 400.0)
+
+
+def test_growth_factor_data_term_differs_by_constant():
+    """Per-voxel growth factor (a variant the paper's data model allows): psi_data with
+    the coefficients of D+ equals the likelihood written straight from eq. data_model,
+    mean counts Nbar R (1 + b D+ delta), up to a constant."""
+    mk = make_mock(CONFIGS["tiny8x2"])
+    g = _growth(mk)
+    alpha, beta, _ = model.coefficients(mk["R"], mk["counts"], mk["bias"], mk["nbar"], g)
+    rng = np.random.default_rng(15)
+    vals = []
+    for _ in range(4):
+        d = 0.5 * rng.standard_normal(alpha.shape)
+        direct = 0.0
+        for l in range(mk["R"].shape[0]):
+            obs = mk["R"][l] > 0
+            r = mk["R"][l][obs]
+            res = mk["counts"][l][obs] - mk["nbar"][l] * r * (1 + mk["bias"][l] * g[obs] * d[obs])
+            direct += 0.5 * np.sum(res ** 2 / (mk["nbar"][l] * r))
+        vals.append(direct - model.psi_data(d, alpha, beta))
+    assert np.ptp(vals) < 1e-9 * abs(vals[0])
+
+
+def test_growth_factor_bias_conditional_mean():
+    """With D+ the bias conditional's mean D/C from the moments of D+ delta is the
+    minimiser over b of the data-model likelihood (a parabola in b)."""
+    from oracle import gibbs
+    mk = make_mock(CONFIGS["tiny8x2"])
+    g = _growth(mk)
+    rng = np.random.default_rng(16)
+    d = 0.5 * rng.standard_normal(g.shape)
+    mom = gibbs.delta_moments(g * d, mk["R"], mk["counts"])
+    for l in range(mk["R"].shape[0]):
+        obs = mk["R"][l] > 0
+        r, nb = mk["R"][l][obs], mk["nbar"][l]
+
+        def psi(b):
+            res = mk["counts"][l][obs] - nb * r * (1 + b * g[obs] * d[obs])
+            return 0.5 * np.sum(res ** 2 / (nb * r))
+        b0, h = 1.0, 0.5
+        f0, fp, fm = psi(b0), psi(b0 + h), psi(b0 - h)
+        b_min = b0 - h * (fp - fm) / (2 * (fp - 2 * f0 + fm))
+        S1, S2, T = mom[l]
+        assert abs((T - nb * S1) / (nb * S2) - b_min) < 1e-9 * max(1.0, abs(b_min))
