@@ -137,7 +137,8 @@ class Sampler:
     chains: list of dicts with keys n, box, nb, R [c,N,N,N], counts [c,N,N,N]
     (numpy or torch), bias [c], nbar [c], pk [nb] (Mpc/h)^3, and optional
     seed, chain_id, nsteps, eps, alpha_prior, fixed_mask, rj, rj_log_bound,
-    tau_mode, delta_k0 (complex [N,N,N/2+1]).
+    tau_mode, delta_k0 (complex [N,N,N/2+1]), growth ([N,N,N] per-voxel growth factor
+    of the data model; absent: 1).
     """
 
     def __init__(self, chains, device="cuda:0", stream=None):
