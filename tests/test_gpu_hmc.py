@@ -22,8 +22,8 @@ def sampler_for(mk, **kw):
     return Sampler([chain_spec(mk, **kw)])
 
 
-@pytest.mark.parametrize("n,box,nb", SIZES)
-def test_shell_index_and_counts_bit_exact(n, box, nb):
+@pytest.mark.parametrize("n,box,nb", SIZES + [(128, 1000.0, 110), (256, 1500.0, 128)])
+def test_shell_index_and_counts_bit_exact(n, box, nb):       # incl. the most shells a grid fills
     mk = plain_mock(n, box, nb)
     s = sampler_for(mk)
     assert np.array_equal(s.shell_index(0).astype(np.int64), grid.half_shells(n, nb))
@@ -193,3 +193,20 @@ def test_radix_plans_match_oracle(n, box, nb, plan):
         s.close()
     if finals:
         assert finals[0][0] == finals[1][0] and np.array_equal(finals[0][1], finals[1][1])
+
+
+def test_init_rejects_unobserved_subsample_and_empty_shells():
+    """Degenerate inputs the method cannot sample: a subsample without any voxel
+    with R > 0 (the Nbar conditional is improper) and more shells than the grid
+    fills; both fail at init with HMC_EINVAL and a message."""
+    from paper_1306_1821_amd.binding import HmcError
+    mk = plain_mock(16, 500.0, 8, nsub=2)
+    R = np.array(mk["R"])
+    R[1] = 0.0
+    counts = np.array(mk["counts"])
+    counts[1] = 0.0
+    spec = chain_spec(mk, R=R, counts=counts)
+    with pytest.raises(HmcError, match="no voxel with R > 0"):
+        Sampler([spec])
+    with pytest.raises(HmcError, match="no modes"):
+        Sampler([chain_spec(plain_mock(8, 500.0, 4), nb=64, pk=np.full(64, 1e4))])
