@@ -27,6 +27,9 @@ is trained on plain-sampler draws from 64 seeded 128^3 mocks (four subsamples,
 40 shells), applied to the 256^3 survey, and the line reports P(k) ESS/s with
 the learned and the plain mass (4 chains each, equal acceptance) and the
 burn-in lengths of the warm start and of delta = 0.
+
+--oracle-timing times the float64 oracle (the CPU baseline) against the GPU per
+leapfrog step at 32^3, 128^3 and 256^3, and the P(k) ESS/s of both at 32^3.
 """
 import argparse
 import json
@@ -68,7 +71,7 @@ def workload_spec(name, eps):
     cfg = mk["cfg"]
     spec = dict(n=cfg.n, box=cfg.box, nb=cfg.nb, R=mk["R"], counts=mk["counts"], bias=mk["bias"],
                 nbar=mk["nbar"], pk=mk["pk_init"], fixed_mask=cfg.fixed_mask, nsteps=cfg.nsteps,
-                eps=eps, rj=cfg.rj, seed=2013, chain_id=0)
+                eps=cfg.eps if eps is None else eps, rj=cfg.rj, seed=2013, chain_id=0)
     return mk, spec
 
 
@@ -93,6 +96,120 @@ def cpu_baseline(mk, spec, budget_s):
     return dict(value=steps / dt, unit="leapfrog steps/s", cores=workers, kind="oracle",
                 sample=f"{steps} float64 KDK leapfrog steps (one gradient evaluation each) of the "
                        f"{spec['n']}^3 workload, scipy.fft workers={workers}, {dt:.1f} s")
+
+
+def oracle_step_ms(mk, spec, workers, reps=5):
+    """Median host time of one float64 KDK leapfrog step of the oracle (a drift, a
+    gradient evaluation, a kick): each repetition times the integrator with three
+    steps and with one, and takes half the difference."""
+    from oracle import grid, hmc
+    post = hmc.make_posterior(spec["n"], spec["box"], spec["nb"], spec["pk"],
+                              mk["R"].astype(np.float64), mk["counts"].astype(np.float64),
+                              spec["bias"], spec["nbar"], workers=workers)
+    dk = grid.fwd(mk["delta"].astype(np.float64), workers)
+    dk[0, 0, 0] = 0
+    pk = hmc.draw_momentum(post, spec["seed"], 0, 0)
+    hmc.leapfrog(dk, pk, post, spec["eps"], 1)          # warm-up
+    per = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        hmc.leapfrog(dk, pk, post, spec["eps"], 1)
+        t1 = time.perf_counter()
+        hmc.leapfrog(dk, pk, post, spec["eps"], 3)
+        t2 = time.perf_counter()
+        per.append(0.5 * ((t2 - t1) - (t1 - t0)))
+    return 1e3 * float(np.median(per))
+
+
+def gpu_step_ms(mk, spec, ntraj=20):
+    """Wall time per leapfrog step of bare trajectories, and the summed device
+    time of the four passes of one step (x, y twice, z) from HIP events."""
+    import torch
+    from paper_1306_1821_amd.binding import Sampler
+    s = Sampler([spec])
+    s.set_state(0, mk["delta"])
+    for i in range(3):
+        s.trajectory(i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(ntraj):
+        s.trajectory(100 + i)
+    torch.cuda.synchronize()
+    wall = 1e3 * (time.perf_counter() - t0) / (ntraj * spec["nsteps"])
+    s.timing(1)
+    for i in range(3):
+        s.trajectory(1000 + i)
+    ms, launches = s.timing(0)
+    s.close()
+    per = [ms[j] / max(1, launches[j]) for j in range(3)]
+    return wall, per[0] + 2.0 * per[1] + per[2]
+
+
+def oracle_timing_main(args):
+    """Oracle against HIP path per grid size (32^3, 128^3, 256^3 survey workloads):
+    float64 leapfrog step time on all host threads and on one, the GPU's per-step
+    wall and kernel time; then P(k) ESS/s of the 32^3 workload, 4 chains from
+    delta = 0, oracle sweeps against GPU sweeps with the same seeds."""
+    import torch
+    from oracle import gibbs, grid
+    from paper_1306_1821_amd import diagnostics
+    from paper_1306_1821_amd.binding import Sampler
+    workers = os.cpu_count() or 1
+    rows = []
+    for name in ("cfg1", "cfg2", "cfg3"):
+        mk, spec = workload_spec(name, args.eps if name == "cfg3" else None)
+        wall, kern = gpu_step_ms(mk, spec)
+        row = dict(workload=name, n=spec["n"], subsamples=len(spec["bias"]),
+                   gpu_ms_per_step_wall=wall, gpu_ms_per_step_kernels=kern,
+                   oracle_ms_per_step={str(workers): oracle_step_ms(mk, spec, workers),
+                                       "1": oracle_step_ms(mk, spec, 1)})
+        row["speedup_vs_oracle_all_threads"] = row["oracle_ms_per_step"][str(workers)] / wall
+        print(f"[oracle-timing] {json.dumps(row)}", file=sys.stderr, flush=True)
+        rows.append(row)
+        torch.cuda.empty_cache()
+
+    # P(k) ESS/s at 32^3: same chains (seed, chain ids, start) on both sides
+    mk, spec = workload_spec("cfg1", None)
+    m, S = 4, args.oracle_sweeps
+    c = mk["cfg"]
+    specs = [dict(spec, chain_id=i) for i in range(m)]
+    s = Sampler(specs)
+    traces_g = np.zeros((m, S, spec["nb"]))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for sw in range(S):
+        for i, st in enumerate(s.sweep(sw)):
+            traces_g[i, sw] = st["pk"]
+    torch.cuda.synchronize()
+    t_gpu = time.perf_counter() - t0
+    s.close()
+    data = dict(R=mk["R"].astype(np.float64), counts=mk["counts"].astype(np.float64))
+    traces_o = np.zeros_like(traces_g)
+    t0 = time.perf_counter()
+    for i in range(m):
+        ocfg = dict(n=c.n, box=c.box, nb=c.nb, eps=spec["eps"], nsteps=spec["nsteps"],
+                    alpha_prior=1.0, seed=spec["seed"], chain=i, fixed_mask=c.fixed_mask,
+                    rj=spec["rj"], workers=1)
+        state = dict(dk=grid.fwd(np.zeros((c.n,) * 3)), pk=np.array(spec["pk"], np.float64),
+                     bias=np.array(spec["bias"], np.float64), nbar=np.array(spec["nbar"], np.float64))
+        for sw in range(S):
+            o = gibbs.sweep(state, data, ocfg, sw)
+            state = dict(dk=o["dk"], pk=o["pk"], bias=o["bias"], nbar=o["nbar"])
+            traces_o[i, sw] = o["pk"]
+    t_orc = time.perf_counter() - t0
+
+    def summary(tr, t):
+        w = np.log(tr[:, S // 2:])                      # second half: past burn-in
+        ess = np.array([diagnostics.ess_bulk(w[:, :, b]) for b in range(w.shape[2])])
+        rh = np.array([diagnostics.split_rhat(w[:, :, b]) for b in range(w.shape[2])])
+        return dict(seconds=t, ms_per_sweep=1e3 * t / S, ess_median=float(np.median(ess)),
+                    ess_min=float(ess.min()), ess_per_s_median=float(np.median(ess)) / (t / 2),
+                    max_split_rhat=float(rh.max()))
+    out = dict(study="oracle_timing", host_threads=workers, rows=rows,
+               cfg1_ess=dict(chains=m, sweeps=S, window="second half of every chain",
+                             max_abs_dlnP=float(np.abs(np.log(traces_g) - np.log(traces_o)).max()),
+                             gpu=summary(traces_g, t_gpu), oracle_one_thread=summary(traces_o, t_orc)))
+    print(json.dumps(out), flush=True)
 
 
 BATCH_GROUPS = [("grp64", 8), ("grp128", 6), ("grp192", 2)]
@@ -331,6 +448,11 @@ def main():
                     help="posterior correlations, P(k) bands and density maps (128^3)")
     ap.add_argument("--ablation", action="store_true",
                     help="P(k) correlation with and without the joint move (128^3)")
+    ap.add_argument("--oracle-timing", action="store_true",
+                    help="float64 oracle against the GPU per grid size (32^3, 128^3, 256^3) "
+                         "and P(k) ESS/s at 32^3")
+    ap.add_argument("--oracle-sweeps", type=int, default=200,
+                    help="--oracle-timing: sweeps per chain of the 32^3 ESS comparison")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the run, copy a float32 buffer of this size 3 times (a kernel of "
                          "known traffic that scales hardware byte counters)")
@@ -340,6 +462,8 @@ def main():
               "(chains or slabs would shard across GPUs, which this build does not do)",
               file=sys.stderr)
         sys.exit(2)
+    if args.oracle_timing:
+        return oracle_timing_main(args)
     if args.ablation:
         return ablation_main(args)
     if args.posterior:
