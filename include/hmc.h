@@ -87,7 +87,10 @@ typedef struct hmc_config {
                                 of a context and by the joint move of that sweep */
 } hmc_config;
 
-/* Caller-owned device buffers of one chain. */
+/* Caller-owned device buffers of one chain.  R and counts are read at init (the
+   survey support, i.e. the voxels with some R^l > 0, and the static sums of the
+   Nbar conditional) and by every sweep: their contents must not change after
+   hmc_init. */
 typedef struct hmc_buffers {
   const float* R;       /* [c][N][N][N] survey response R^l_i >= 0 */
   const float* counts;  /* [c][N][N][N] galaxy counts N^l_i (0 where R = 0) */
@@ -99,7 +102,7 @@ typedef struct hmc_buffers {
   float* beta;          /* [N][N][N] sum_l b_l (N^l - Nbar_l R^l) (library writes) */
   void* work;           /* workspace, at least hmc_workspace_bytes(cfg) bytes */
   size_t work_bytes;
-  const float* growth;  /* [N][N][N] linear growth factor D+ per voxel of the data model
+  const float* growth;  /* [N][N][N] linear growth factor D+ > 0 per voxel of the data model
                            (eq. data_model: mean counts Nbar R (1 + b D+ delta)), or NULL
                            for D+ = 1 (the paper's experiments) */
 } hmc_buffers;

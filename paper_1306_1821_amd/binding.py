@@ -44,7 +44,9 @@ class HmcSweepStats(ctypes.Structure):
 EXPORTS = ["hmc_workspace_bytes", "hmc_init", "hmc_init_batch", "leapfrog_trajectory",
            "leapfrog_trajectory_async", "gibbs_sweep_async", "hmc_sweep_record_doubles",
            "hamiltonian", "shell_power", "gibbs_sweep", "hmc_set_state", "hmc_set_params",
-           "hmc_set_step", "hmc_warm_start", "hmc_set_launch", "hmc_set_plan", "hmc_get_launch", "hmc_autotune", "hmc_set_coefficients", "hmc_get_params", "hmc_shell_index", "hmc_set_mass", "hmc_set_mass_diagonal", "hmc_field_moments",
+           "hmc_set_step", "hmc_warm_start", "hmc_set_launch", "hmc_set_plan", "hmc_get_launch",
+           "hmc_autotune", "hmc_set_coefficients", "hmc_get_params", "hmc_shell_index",
+           "hmc_set_mass", "hmc_set_mass_diagonal", "hmc_field_moments",
            "hmc_timing", "hmc_use_graph", "hmc_last_error", "hmc_destroy",
            "cnn_param_count", "cnn_create", "cnn_get_params", "cnn_forward", "cnn_gradient",
            "cnn_features",

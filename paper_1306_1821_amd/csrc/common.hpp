@@ -101,6 +101,9 @@ struct ChainDev {
   float2* shat;
   float* smass;
   signed char* lut;  // shell index of every q = |k|^2 in grid units (-1 at q = 0)
+  // survey support: bit g of word w is set when one of the 4 voxels of group
+  // 64 w + g (voxels 4 (64 w + g) .. + 3) has R^l > 0 for some subsample l
+  unsigned long long* obs;
 };
 
 // Twiddle tables W_L^i = exp(-2 pi i i / L), float2, for every supported

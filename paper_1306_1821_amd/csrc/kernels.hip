@@ -530,6 +530,9 @@ typedef float bin_t;
 #else
 typedef double bin_t;
 #endif
+#ifndef HMC_OBSMASK
+#define HMC_OBSMASK 1  // coefficient and moment passes skip groups outside the survey support
+#endif
 #ifndef HMC_DOT_COPIES
 #define HMC_DOT_COPIES 2
 #endif
@@ -1500,6 +1503,32 @@ __device__ __forceinline__ void gst4(float* base, uint32_t i4, f4v v) {
   *(gf4v*)((gchar*)base + i4 * 16u) = v;
 }
 
+// Survey support bitmask (once at init; R must not change afterwards).  A wave
+// covers 64 consecutive 4-voxel groups starting at a multiple of 64 (tiles hold
+// 4096 groups, N^3 / 4 is a multiple of 64), so its ballot is one mask word.
+__global__ void __launch_bounds__(kThreads) k_obs_mask(const ChainDev* __restrict__ ch, int nch,
+                                                        int total) {
+  for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
+    const ChainDev& d = ch[find_chain(ch, nch, tile, kTileR)];
+    const int lt = tile - d.tb[kTileR];
+    const uint32_t nv4 = (uint32_t)(d.nv / 4), base4 = (uint32_t)lt * (kElemPerTile / 4);
+    for (uint32_t j = threadIdx.x; j < kElemPerTile / 4; j += kThreads) {
+      const uint32_t i4 = base4 + j;
+      if (i4 >= nv4) break;  // wave-uniform (see above)
+      bool o = false;
+      for (int l = 0; l < d.nsub; ++l) {
+        const f4v r = gld4(d.R + (size_t)l * d.nv, i4);
+        o |= (r[0] > 0.f) | (r[1] > 0.f) | (r[2] > 0.f) | (r[3] > 0.f);
+      }
+      const unsigned long long word = __ballot(o);
+      if ((threadIdx.x & 63) == 0) d.obs[i4 >> 6] = word;
+    }
+  }
+}
+__device__ __forceinline__ bool observed(const ChainDev& d, uint32_t i4) {
+  return HMC_OBSMASK == 0 || ((d.obs[i4 >> 6] >> (i4 & 63)) & 1ull);
+}
+
 __global__ void __launch_bounds__(kThreads) k_coeff(const ChainDev* __restrict__ ch, int nch,
                                                      int total) {
   __shared__ double red[4];
@@ -1520,23 +1549,25 @@ __global__ void __launch_bounds__(kThreads) k_coeff(const ChainDev* __restrict__
       const uint32_t i4 = base4 + j;
       if (i4 >= nv4) break;
       f4v al = {0.f, 0.f, 0.f, 0.f}, be = {0.f, 0.f, 0.f, 0.f};
-      for (int l = 0; l < d.nsub; ++l) {
-        const f4v r = gld4(d.R + (size_t)l * d.nv, i4);
-        const f4v c = gld4(d.counts + (size_t)l * d.nv, i4);
+      if (observed(d, i4)) {  // outside the support R^l = 0: alpha = beta = 0, no loads
+        for (int l = 0; l < d.nsub; ++l) {
+          const f4v r = gld4(d.R + (size_t)l * d.nv, i4);
+          const f4v c = gld4(d.counts + (size_t)l * d.nv, i4);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          if (r[q] > 0.f) {
-            al[q] += cb2n[l] * r[q];
-            be[q] += cb[l] * (c[q] - cn[l] * r[q]);
+          for (int q = 0; q < 4; ++q) {
+            if (r[q] > 0.f) {
+              al[q] += cb2n[l] * r[q];
+              be[q] += cb[l] * (c[q] - cn[l] * r[q]);
+            }
           }
         }
-      }
-      if (d.growth) {  // per-voxel growth factor: b -> b D+ in the data model
-        const f4v g = gld4(d.growth, i4);
+        if (d.growth) {  // per-voxel growth factor: b -> b D+ in the data model
+          const f4v g = gld4(d.growth, i4);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          al[q] *= g[q] * g[q];
-          be[q] *= g[q];
+          for (int q = 0; q < 4; ++q) {
+            al[q] *= g[q] * g[q];
+            be[q] *= g[q];
+          }
         }
       }
       gst4(d.alpha, i4, al);
@@ -1615,6 +1646,7 @@ __global__ void __launch_bounds__(kThreads) k_moments(const ChainDev* __restrict
       for (uint32_t j = threadIdx.x; j < kElemPerTile / 4; j += kThreads) {
         const uint32_t i4 = base4 + j;
         if (i4 >= nv4) break;
+        if (!observed(d, i4)) continue;  // R^l = 0 on all 4 voxels: no contribution
         const f4v r = gld4(d.R + (size_t)l * d.nv, i4);
         const f4v c = gld4(d.counts + (size_t)l * d.nv, i4);
         const f4v x = gld4(d.dr, i4);
@@ -2120,6 +2152,9 @@ void launch_alpha_sum(const ChainDev* ch, int nch, int total, hipStream_t s) {
 }
 void launch_static_moments(const ChainDev* ch, int nch, int total, hipStream_t s) {
   hipLaunchKernelGGL(k_static_moments, dim3(eg(total)), dim3(kThreads), 0, s, ch, nch, total);
+}
+void launch_obs_mask(const ChainDev* ch, int nch, int total, hipStream_t s) {
+  hipLaunchKernelGGL(k_obs_mask, dim3(eg(total)), dim3(kThreads), 0, s, ch, nch, total);
 }
 void launch_moments(const ChainDev* ch, int nch, int total, hipStream_t s) {
   hipLaunchKernelGGL(k_moments, dim3(eg(total)), dim3(kThreads), 0, s, ch, nch, total);

@@ -76,6 +76,7 @@ void launch_warm_combine(const ChainDev* ch, int total_r, const float* mu, const
 void launch_coeff(const ChainDev* ch, int nch, int total, hipStream_t s);
 void launch_alpha_sum(const ChainDev* ch, int nch, int total, hipStream_t s);
 void launch_static_moments(const ChainDev* ch, int nch, int total, hipStream_t s);
+void launch_obs_mask(const ChainDev* ch, int nch, int total, hipStream_t s);
 void launch_moments(const ChainDev* ch, int nch, int total, hipStream_t s);
 void launch_energy_k(const ChainDev* ch, int nch, int total, hipStream_t s);
 void launch_energy_r(const ChainDev* ch, int nch, int total, hipStream_t s);

@@ -36,7 +36,7 @@ struct Chain {
 };
 
 struct WsLayout {
-  size_t T, bdk, bgk, drn, part, shpart, mpart, T2, T3, shat, smass, lut, total;
+  size_t T, bdk, bgk, drn, part, shpart, mpart, T2, T3, shat, smass, lut, obs, total;
   int maxtiles;
 };
 
@@ -74,6 +74,7 @@ WsLayout layout(const hmc_config& c) {
   L.shat = off; off = align256(off + nh * 8);
   L.smass = off; off = align256(off + nv * 4);
   L.lut = off; off = align256(off + 3 * (size_t)(c.n / 2) * (c.n / 2) + 1);
+  L.obs = off; off = align256(off + nv / 256 * 8);  // one bit per 4 voxels
   L.total = off;
   return L;
 }
@@ -525,6 +526,7 @@ hmc_status hmc_init_batch(const hmc_config* cfg, const hmc_buffers* buf, int32_t
     d.shat = (float2*)(w + L.shat);
     d.smass = (float*)(w + L.smass);
     d.lut = (signed char*)(w + L.lut);
+    d.obs = (unsigned long long*)(w + L.obs);
     if (hipMalloc(&d.P, kPSize * sizeof(double)) != hipSuccess ||
         hipMalloc(&d.tf, kTSize * sizeof(float)) != hipSuccess ||
         hipMalloc(&d.td, kDSize * sizeof(double)) != hipSuccess ||
@@ -590,7 +592,9 @@ hmc_status hmc_init_batch(const hmc_config* cfg, const hmc_buffers* buf, int32_t
   if ((st = upload_desc(c)) != HMC_OK) return bail(st);
   const int nch = n_chains;
   for (auto& k : c->ch) launch_shell_lut(k.solo, k.cfg.n, c->stream);
-  // static data sums, mode counts, coefficients, tables, gradient of the initial state
+  // survey support, static data sums, mode counts, coefficients, tables, gradient of
+  // the initial state
+  launch_obs_mask(c->d_all, nch, c->total[kTileR], c->stream);
   launch_static_moments(c->d_all, nch, c->total[kTileR], c->stream);
   launch_colsum(c->d_all, nch, 3 * c->max_sub, 1, kTileR, kS0, 1, c->stream);
   launch_shell_power(c->d_all, nch, c->total[kTileK], c->stream);
