@@ -1525,6 +1525,7 @@ __global__ void __launch_bounds__(kThreads) k_obs_mask(const ChainDev* __restric
     }
   }
 }
+constexpr int kSubChunk = 8;  // subsamples per unrolled group in the data passes
 __device__ __forceinline__ bool observed(const ChainDev& d, uint32_t i4) {
   return HMC_OBSMASK == 0 || ((d.obs[i4 >> 6] >> (i4 & 63)) & 1ull);
 }
@@ -1550,14 +1551,19 @@ __global__ void __launch_bounds__(kThreads) k_coeff(const ChainDev* __restrict__
       if (i4 >= nv4) break;
       f4v al = {0.f, 0.f, 0.f, 0.f}, be = {0.f, 0.f, 0.f, 0.f};
       if (observed(d, i4)) {  // outside the support R^l = 0: alpha = beta = 0, no loads
-        for (int l = 0; l < d.nsub; ++l) {
-          const f4v r = gld4(d.R + (size_t)l * d.nv, i4);
-          const f4v c = gld4(d.counts + (size_t)l * d.nv, i4);
+        for (int l0 = 0; l0 < d.nsub; l0 += kSubChunk) {  // a chunk's loads in flight together
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            if (r[q] > 0.f) {
-              al[q] += cb2n[l] * r[q];
-              be[q] += cb[l] * (c[q] - cn[l] * r[q]);
+          for (int u = 0; u < kSubChunk; ++u) {
+            const int l = l0 + u;
+            if (l >= d.nsub) break;
+            const f4v r = gld4(d.R + (size_t)l * d.nv, i4);
+            const f4v c = gld4(d.counts + (size_t)l * d.nv, i4);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              if (r[q] > 0.f) {
+                al[q] += cb2n[l] * r[q];
+                be[q] += cb[l] * (c[q] - cn[l] * r[q]);
+              }
             }
           }
         }
@@ -1633,42 +1639,59 @@ __global__ void __launch_bounds__(kThreads) k_static_moments(const ChainDev* __r
   }
 }
 
-// S1 = sum R delta, S2 = sum R delta^2, T = sum N delta per subsample (R > 0)
+// S1 = sum R delta, S2 = sum R delta^2, T = sum N delta per subsample (R > 0).
+// Subsamples go in chunks of kSubChunk per pass over the tile: a thread keeps the
+// chunk's 3 kSubChunk sums in registers and has the chunk's loads in flight
+// together; per sum the block reduction is block_sum's (butterfly per wave, waves
+// added in order).
 __global__ void __launch_bounds__(kThreads) k_moments(const ChainDev* __restrict__ ch, int nch,
                                                        int total) {
-  __shared__ double red[4];
+  constexpr int V = 3 * kSubChunk;
+  __shared__ double red[4 * V];
   for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
     const ChainDev& d = ch[find_chain(ch, nch, tile, kTileR)];
     const int lt = tile - d.tb[kTileR];
     const uint32_t nv4 = (uint32_t)(d.nv / 4), base4 = (uint32_t)lt * (kElemPerTile / 4);
-    for (int l = 0; l < d.nsub; ++l) {
-      double s1 = 0.0, s2 = 0.0, st = 0.0;
+    for (int l0 = 0; l0 < d.nsub; l0 += kSubChunk) {
+      double sm[V];
+#pragma unroll
+      for (int u = 0; u < V; ++u) sm[u] = 0.0;
       for (uint32_t j = threadIdx.x; j < kElemPerTile / 4; j += kThreads) {
         const uint32_t i4 = base4 + j;
         if (i4 >= nv4) break;
         if (!observed(d, i4)) continue;  // R^l = 0 on all 4 voxels: no contribution
-        const f4v r = gld4(d.R + (size_t)l * d.nv, i4);
-        const f4v c = gld4(d.counts + (size_t)l * d.nv, i4);
         const f4v x = gld4(d.dr, i4);
         const f4v g = d.growth ? gld4(d.growth, i4) : f4v{1.f, 1.f, 1.f, 1.f};
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          if (r[q] > 0.f) {
-            const double xq = (double)x[q] * (double)g[q];  // D+ delta
-            s1 += (double)r[q] * xq;
-            s2 += (double)r[q] * xq * xq;
-            st += (double)c[q] * xq;
+        for (int u = 0; u < kSubChunk; ++u) {
+          const int l = l0 + u;
+          if (l >= d.nsub) break;
+          const f4v r = gld4(d.R + (size_t)l * d.nv, i4);
+          const f4v c = gld4(d.counts + (size_t)l * d.nv, i4);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            if (r[q] > 0.f) {
+              const double xq = (double)x[q] * (double)g[q];  // D+ delta
+              sm[3 * u] += (double)r[q] * xq;
+              sm[3 * u + 1] += (double)r[q] * xq * xq;
+              sm[3 * u + 2] += (double)c[q] * xq;
+            }
           }
         }
       }
-      s1 = block_sum(s1, red);
-      s2 = block_sum(s2, red);
-      st = block_sum(st, red);
-      if (threadIdx.x == 0) {
-        double* o = d.mpart + (size_t)lt * 3 * d.nsub + 3 * l;
-        o[0] = s1;
-        o[1] = s2;
-        o[2] = st;
+#pragma unroll
+      for (int u = 0; u < V; ++u) sm[u] = wave_sum(sm[u]);
+      __syncthreads();  // red of the previous chunk / tile consumed
+      if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int u = 0; u < V; ++u) red[(threadIdx.x >> 6) * V + u] = sm[u];
+      }
+      __syncthreads();
+      const int nl = d.nsub - l0 < kSubChunk ? d.nsub - l0 : kSubChunk;
+      if ((int)threadIdx.x < 3 * nl) {
+        const int u = threadIdx.x;
+        d.mpart[(size_t)lt * 3 * d.nsub + 3 * l0 + u] =
+            red[u] + red[V + u] + red[2 * V + u] + red[3 * V + u];
       }
     }
     __syncthreads();
@@ -1696,11 +1719,12 @@ __global__ void __launch_bounds__(kThreads) k_energy_r(const ChainDev* __restric
 }
 
 __device__ __forceinline__ void kindex(long long i, int n, int* fx, int* fy, int* kz) {
-  const int h = n / 2 + 1;
-  *kz = (int)(i % h);
-  const long long r = i / h;
-  *fy = sfreq((int)(r % n), n);
-  *fx = sfreq((int)(r / n), n);
+  // i < N^2 (N/2 + 1) < 2^31 for every supported N: 32-bit unsigned arithmetic
+  const uint32_t u = (uint32_t)i, h = (uint32_t)(n / 2 + 1), un = (uint32_t)n;
+  const uint32_t r = u / h, x = r / un;
+  *kz = (int)(u - r * h);
+  *fy = sfreq((int)(r - x * un), n);
+  *fx = sfreq((int)x, n);
 }
 
 // kinetic and prior energies on mom_k, delta_k
@@ -1734,8 +1758,10 @@ __global__ void __launch_bounds__(kThreads) k_energy_k(const ChainDev* __restric
 }
 
 // shell sums sigma_m and mode counts n_m (full-grid weights) per tile
+// with_counts: also the weighted mode counts per shell (init only; the sweep's P
+// draw needs sigma alone)
 __global__ void __launch_bounds__(kThreads) k_shell_power(const ChainDev* __restrict__ ch,
-                                                           int nch, int total) {
+                                                           int nch, int total, int with_counts) {
   __shared__ double bins[4 * kMaxBins];
   __shared__ double cnt[4 * kMaxBins];
   for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
@@ -1757,14 +1783,15 @@ __global__ void __launch_bounds__(kThreads) k_shell_power(const ChainDev* __rest
       const double w = (kz == 0 || kz == d.n / 2) ? 1.0 : 2.0;
       const float2 x = d.dk[i];
       atomicAdd(&bins[wv + m], w * ((double)x.x * x.x + (double)x.y * x.y));
-      atomicAdd(&cnt[wv + m], w);
+      if (with_counts) atomicAdd(&cnt[wv + m], w);
     }
     __syncthreads();
     for (int m = threadIdx.x; m < d.nb; m += kThreads) {
       d.shpart[(size_t)lt * d.nb + m] =
           ((bins[m] + bins[kMaxBins + m]) + bins[2 * kMaxBins + m]) + bins[3 * kMaxBins + m];
-      d.mpart[(size_t)lt * d.nb + m] =
-          ((cnt[m] + cnt[kMaxBins + m]) + cnt[2 * kMaxBins + m]) + cnt[3 * kMaxBins + m];
+      if (with_counts)
+        d.mpart[(size_t)lt * d.nb + m] =
+            ((cnt[m] + cnt[kMaxBins + m]) + cnt[2 * kMaxBins + m]) + cnt[3 * kMaxBins + m];
     }
     __syncthreads();
   }
@@ -2165,8 +2192,9 @@ void launch_energy_k(const ChainDev* ch, int nch, int total, hipStream_t s) {
 void launch_energy_r(const ChainDev* ch, int nch, int total, hipStream_t s) {
   hipLaunchKernelGGL(k_energy_r, dim3(eg(total)), dim3(kThreads), 0, s, ch, nch, total);
 }
-void launch_shell_power(const ChainDev* ch, int nch, int total, hipStream_t s) {
-  hipLaunchKernelGGL(k_shell_power, dim3(eg(total)), dim3(kThreads), 0, s, ch, nch, total);
+void launch_shell_power(const ChainDev* ch, int nch, int total, hipStream_t s, int with_counts) {
+  hipLaunchKernelGGL(k_shell_power, dim3(eg(total)), dim3(kThreads), 0, s, ch, nch, total,
+                     with_counts);
 }
 void launch_shell_index(const ChainDev* ch, int total, int16_t* out, hipStream_t s) {
   hipLaunchKernelGGL(k_shell_index, dim3(eg(total)), dim3(kThreads), 0, s, ch, total, out);

@@ -80,7 +80,8 @@ void launch_obs_mask(const ChainDev* ch, int nch, int total, hipStream_t s);
 void launch_moments(const ChainDev* ch, int nch, int total, hipStream_t s);
 void launch_energy_k(const ChainDev* ch, int nch, int total, hipStream_t s);
 void launch_energy_r(const ChainDev* ch, int nch, int total, hipStream_t s);
-void launch_shell_power(const ChainDev* ch, int nch, int total, hipStream_t s);
+void launch_shell_power(const ChainDev* ch, int nch, int total, hipStream_t s,
+                        int with_counts = 0);
 void launch_shell_index(const ChainDev* ch, int total, int16_t* out, hipStream_t s);
 void launch_commit(int what, const ChainDev* ch, int nch, int total_k, int total_r,
                    hipStream_t s);

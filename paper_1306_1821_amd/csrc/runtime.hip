@@ -597,7 +597,7 @@ hmc_status hmc_init_batch(const hmc_config* cfg, const hmc_buffers* buf, int32_t
   launch_obs_mask(c->d_all, nch, c->total[kTileR], c->stream);
   launch_static_moments(c->d_all, nch, c->total[kTileR], c->stream);
   launch_colsum(c->d_all, nch, 3 * c->max_sub, 1, kTileR, kS0, 1, c->stream);
-  launch_shell_power(c->d_all, nch, c->total[kTileK], c->stream);
+  launch_shell_power(c->d_all, nch, c->total[kTileK], c->stream, 1);
   launch_colsum(c->d_all, nch, c->max_nb, 1, kTileK, kNmodes, 0, c->stream);
   launch_colsum(c->d_all, nch, c->max_nb, 0, kTileK, kSigma, 0, c->stream);
   if ((st = refresh_coefficients(c)) != HMC_OK) return bail(st);
