@@ -1812,6 +1812,8 @@ __global__ void __launch_bounds__(kThreads) k_shell_index(const ChainDev* __rest
 // rejected chains restore delta_hat and g_hat from the backups, accepted chains
 // take the proposal's real field.  After a joint move, accepted chains rescale
 // delta_hat per shell and take the move's g_hat and real field.
+// k-space arrays move two complex entries (16 bytes) per access: N^2 (N/2 + 1)
+// and the tile size are even
 __global__ void __launch_bounds__(kThreads) k_commit_k(const ChainDev* __restrict__ ch, int nch,
                                                         int total, int what) {
   for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
@@ -1820,19 +1822,27 @@ __global__ void __launch_bounds__(kThreads) k_commit_k(const ChainDev* __restric
     const bool acc = what == C_HMC ? d.P[kAcc] != 0.0 : d.P[kRjAcc] != 0.0;
     if (what == C_HMC && acc) continue;
     if (what == C_RJ && !acc) continue;
-    for (int j = threadIdx.x; j < kElemPerTile; j += kThreads) {
-      const long long i = (long long)lt * kElemPerTile + j;
-      if (i >= d.nh) break;
+    const uint32_t nh2 = (uint32_t)(d.nh / 2), base2 = (uint32_t)lt * (kElemPerTile / 2);
+    float* dk = (float*)d.dk;
+    float* gk = (float*)d.gk;
+    for (uint32_t j = threadIdx.x; j < kElemPerTile / 2; j += kThreads) {
+      const uint32_t i2 = base2 + j;
+      if (i2 >= nh2) break;
+      gst4(gk, i2, gld4((const float*)d.bgk, i2));
       if (what == C_HMC) {
-        d.dk[i] = d.bdk[i];
-        d.gk[i] = d.bgk[i];
+        gst4(dk, i2, gld4((const float*)d.bdk, i2));
       } else {
-        int fx, fy, kz;
-        kindex(i, d.n, &fx, &fy, &kz);
-        const int m = shell_of(d, fx, fy, kz);
-        const float s = m >= 0 ? d.tf[kTScale + m] : 0.f;
-        d.dk[i] = cscale(d.dk[i], s);
-        d.gk[i] = d.bgk[i];
+        f4v v = gld4(dk, i2);
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          int fx, fy, kz;
+          kindex(2 * (long long)i2 + e, d.n, &fx, &fy, &kz);
+          const int m = shell_of(d, fx, fy, kz);
+          const float sc = m >= 0 ? d.tf[kTScale + m] : 0.f;
+          v[2 * e] *= sc;
+          v[2 * e + 1] *= sc;
+        }
+        gst4(dk, i2, v);
       }
     }
   }
@@ -1844,10 +1854,11 @@ __global__ void __launch_bounds__(kThreads) k_commit_r(const ChainDev* __restric
     const int lt = tile - d.tb[kTileR];
     const bool acc = what == C_HMC ? d.P[kAcc] != 0.0 : d.P[kRjAcc] != 0.0;
     if (!acc) continue;
-    for (int j = threadIdx.x; j < kElemPerTile; j += kThreads) {
-      const long long i = (long long)lt * kElemPerTile + j;
-      if (i >= d.nv) break;
-      d.dr[i] = d.drn[i];
+    const uint32_t nv4 = (uint32_t)(d.nv / 4), base4 = (uint32_t)lt * (kElemPerTile / 4);
+    for (uint32_t j = threadIdx.x; j < kElemPerTile / 4; j += kThreads) {
+      const uint32_t i4 = base4 + j;
+      if (i4 >= nv4) break;
+      gst4(d.dr, i4, gld4(d.drn, i4));
     }
   }
 }
