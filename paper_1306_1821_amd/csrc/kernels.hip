@@ -1758,10 +1758,17 @@ __global__ void __launch_bounds__(kThreads) k_energy_k(const ChainDev* __restric
 }
 
 // shell sums sigma_m and mode counts n_m (full-grid weights) per tile
-// with_counts: also the weighted mode counts per shell (init only; the sweep's P
-// draw needs sigma alone)
-__global__ void __launch_bounds__(kThreads) k_shell_power(const ChainDev* __restrict__ ch,
-                                                           int nch, int total, int with_counts) {
+// Per-shell sums over k-space tiles into shpart[tile][m] (weights w = 1 on the
+// kz = 0, N/2 planes, 2 elsewhere; k = 0 excluded), one bin copy per wave; the
+// shell index comes from the branch-free integer rule (no table loads):
+//   SP_POWER: sum w |delta_hat|^2 (sigma_m), with counts also sum w (mode counts,
+//             into mpart; init only, the sweep's P draw needs sigma alone);
+//   SP_DOT:   sum w Re(conj(delta_hat) g_hat) of the stored state and gradient
+//             (the joint move's dU at its start).
+enum ShellSum : int { SP_POWER = 0, SP_DOT = 1 };
+template <int WHAT>
+__global__ void __launch_bounds__(kThreads) k_shell_sum(const ChainDev* __restrict__ ch,
+                                                         int nch, int total, int with_counts) {
   __shared__ double bins[4 * kMaxBins];
   __shared__ double cnt[4 * kMaxBins];
   for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
@@ -1773,23 +1780,32 @@ __global__ void __launch_bounds__(kThreads) k_shell_power(const ChainDev* __rest
     }
     __syncthreads();
     const int wv = (threadIdx.x >> 6) * kMaxBins;
+    const uint32_t qmax = 3u * (uint32_t)(d.n / 2) * (uint32_t)(d.n / 2), nbu = (uint32_t)d.nb;
+    const float inv_qmax = 1.f / (float)qmax;
     for (int j = threadIdx.x; j < kElemPerTile; j += kThreads) {
       const long long i = (long long)lt * kElemPerTile + j;
       if (i >= d.nh) break;
       int fx, fy, kz;
       kindex(i, d.n, &fx, &fy, &kz);
-      const int m = shell_of(d, fx, fy, kz);
+      const int m = shell_fast((uint32_t)(fx * fx + fy * fy + kz * kz), qmax, inv_qmax, nbu);
       if (m < 0) continue;
       const double w = (kz == 0 || kz == d.n / 2) ? 1.0 : 2.0;
       const float2 x = d.dk[i];
-      atomicAdd(&bins[wv + m], w * ((double)x.x * x.x + (double)x.y * x.y));
-      if (with_counts) atomicAdd(&cnt[wv + m], w);
+      double val;
+      if constexpr (WHAT == SP_POWER) {
+        val = w * ((double)x.x * x.x + (double)x.y * x.y);
+      } else {
+        const float2 g = d.gk[i];
+        val = w * ((double)x.x * g.x + (double)x.y * g.y);
+      }
+      atomicAdd(&bins[wv + m], val);
+      if (WHAT == SP_POWER && with_counts) atomicAdd(&cnt[wv + m], w);
     }
     __syncthreads();
     for (int m = threadIdx.x; m < d.nb; m += kThreads) {
       d.shpart[(size_t)lt * d.nb + m] =
           ((bins[m] + bins[kMaxBins + m]) + bins[2 * kMaxBins + m]) + bins[3 * kMaxBins + m];
-      if (with_counts)
+      if (WHAT == SP_POWER && with_counts)
         d.mpart[(size_t)lt * d.nb + m] =
             ((cnt[m] + cnt[kMaxBins + m]) + cnt[2 * kMaxBins + m]) + cnt[3 * kMaxBins + m];
     }
@@ -2204,8 +2220,11 @@ void launch_energy_r(const ChainDev* ch, int nch, int total, hipStream_t s) {
   hipLaunchKernelGGL(k_energy_r, dim3(eg(total)), dim3(kThreads), 0, s, ch, nch, total);
 }
 void launch_shell_power(const ChainDev* ch, int nch, int total, hipStream_t s, int with_counts) {
-  hipLaunchKernelGGL(k_shell_power, dim3(eg(total)), dim3(kThreads), 0, s, ch, nch, total,
+  hipLaunchKernelGGL(k_shell_sum<SP_POWER>, dim3(eg(total)), dim3(kThreads), 0, s, ch, nch, total,
                      with_counts);
+}
+void launch_shell_dot(const ChainDev* ch, int nch, int total, hipStream_t s) {
+  hipLaunchKernelGGL(k_shell_sum<SP_DOT>, dim3(eg(total)), dim3(kThreads), 0, s, ch, nch, total, 0);
 }
 void launch_shell_index(const ChainDev* ch, int total, int16_t* out, hipStream_t s) {
   hipLaunchKernelGGL(k_shell_index, dim3(eg(total)), dim3(kThreads), 0, s, ch, total, out);
@@ -2249,8 +2268,8 @@ void launch_draw_power(const ChainDev* ch, int nch, hipStream_t s) {
 void launch_draw_nbar_bias(const ChainDev* ch, int nch, hipStream_t s) {
   hipLaunchKernelGGL(k_draw_nbar_bias, dim3(nch), dim3(64), 0, s, ch);
 }
-void launch_rj(int phase, const ChainDev* ch, int nch, int nb_max, hipStream_t s) {
-  launch_colsum(ch, nch, nb_max, 0, kTileXY, kDU, 2, s);  // dU from the last x pass
+void launch_rj(int phase, const ChainDev* ch, int nch, int nb_max, hipStream_t s, int cls) {
+  launch_colsum(ch, nch, nb_max, 0, cls, kDU, 2, s);  // dU from the per-tile shell dots
   hipLaunchKernelGGL(k_rj, dim3(nch), dim3(kThreads), 0, s, ch, phase);
 }
 

@@ -80,6 +80,7 @@ void launch_obs_mask(const ChainDev* ch, int nch, int total, hipStream_t s);
 void launch_moments(const ChainDev* ch, int nch, int total, hipStream_t s);
 void launch_energy_k(const ChainDev* ch, int nch, int total, hipStream_t s);
 void launch_energy_r(const ChainDev* ch, int nch, int total, hipStream_t s);
+void launch_shell_dot(const ChainDev* ch, int nch, int total, hipStream_t s);
 void launch_shell_power(const ChainDev* ch, int nch, int total, hipStream_t s,
                         int with_counts = 0);
 void launch_shell_index(const ChainDev* ch, int total, int16_t* out, hipStream_t s);
@@ -101,7 +102,8 @@ void launch_set_draw(uint32_t* p, uint32_t v, hipStream_t s);
 void launch_accept(const ChainDev* ch, int nch, hipStream_t s);
 void launch_draw_power(const ChainDev* ch, int nch, hipStream_t s);
 void launch_draw_nbar_bias(const ChainDev* ch, int nch, hipStream_t s);
-void launch_rj(int phase, const ChainDev* ch, int nch, int nb_max, hipStream_t s);
+void launch_rj(int phase, const ChainDev* ch, int nch, int nb_max, hipStream_t s,
+               int cls = kTileXY);
 
 enum Commit : int { C_HMC = 0, C_RJ = 1 };
 enum RjPhase : int { RJ_BEGIN = 0, RJ_STEP = 1, RJ_END = 2 };

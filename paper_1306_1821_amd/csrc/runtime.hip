@@ -773,13 +773,12 @@ static hmc_status run_sweep(hmc_ctx* c) {
   for (auto& k : c->ch) any_rj |= k.cfg.rj_move != 0;
   if (any_rj) {
     Seq q = seq_all(c);
-    // dU at the start: per-shell Re(conj(delta_hat) g_hat) at the current state
-    q.x(X_INV, 0.f, 0.f, 0);
-    q.y(-1);
-    q.z(Z_GRAD, 0);
-    q.y(+1);
-    q.x(X_FWD, 0.f, 0.f, XF_DOT | XF_NOSTORE);
-    launch_rj(RJ_BEGIN, c->d_all, nch, c->max_nb, c->stream);
+    // dU at the start: per-shell Re(conj(delta_hat) g_hat) at the current state.
+    // grad_k holds g_hat of delta_hat here (the trajectory's last gradient, or the
+    // restored one of its start; the P draw does not change alpha, beta), so one
+    // k-space pass over the stored arrays gives it.
+    launch_shell_dot(c->d_all, nch, c->total[kTileK], c->stream);
+    launch_rj(RJ_BEGIN, c->d_all, nch, c->max_nb, c->stream, kTileK);
     for (int i = 0; i < c->cur_steps; ++i) {
       const bool last = i == c->cur_steps - 1;
       q.gradient(last ? (ZF_WRITE_DRN | ZF_DATA) : 0,
