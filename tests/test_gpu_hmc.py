@@ -135,6 +135,30 @@ def test_trajectory_matches_oracle(case, eps, nsteps):
     s.close()
 
 
+@pytest.mark.parametrize("eps,accepted", [(0.02, True), (0.8, False)])
+def test_gradient_cache_after_trajectory(eps, accepted):
+    """After a trajectory, accepted (small step) or rejected (eps = 0.8: dH of 50-70 in
+    the oracle), grad_k holds F(alpha delta - beta) of the state's delta_hat: the next
+    trajectory's first kick and the joint move's start read it from there."""
+    mk = mock("small16")
+    a32, b32 = coefficients32(mk)
+    s = sampler_for(mk, eps=eps, nsteps=10, seed=31)
+    s.set_coefficients(0, a32, b32)
+    d32, _ = start_state(mk)
+    s.set_state(0, d32)
+    post = oracle_posterior(mk, a32, b32)
+    for traj in range(2):
+        dH, acc = s.trajectory(traj)
+        assert bool(acc[0]) == accepted, (traj, dH[0])
+        st = s.state(0)
+        _, gk, _ = model.force_k(st["delta_k"].astype(np.complex128), post.lam_k, post.alpha,
+                                 post.beta)
+        err = rel_l2(st["grad_k"], np.where(post.shells >= 0, gk, 0))
+        print(f"eps {eps} traj {traj}: dH {dH[0]:.4e} accepted {acc[0]}, grad_k rel-L2 {err:.2e}")
+        assert err < 1e-5
+    s.close()
+
+
 def test_batched_mixed_sizes_match_oracle():
     """Chains of 8^3, 16^3 and 32^3 advance in the same launches; each matches the oracle."""
     names = ["tiny8x2", "small16", "cfg1"]
