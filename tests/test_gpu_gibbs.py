@@ -49,12 +49,40 @@ def test_flat_power_prior_sweeps_match_oracle(rj):
 def test_growth_factor_sweeps_match_oracle(rj):
     """A per-voxel growth factor D+ in the data model (a variant the paper allows):
     coefficients and the Nbar, b conditionals use D+ delta."""
-    mk = case_mock("cfg1")
+    run_sweeps("cfg1", rj, 0.05, 20, growth=radial_growth(case_mock("cfg1")))
+
+
+def radial_growth(mk):
     n, box = mk["cfg"].n, mk["cfg"].box
     c = (np.arange(n) + 0.5) * box / n - 0.5 * box
     r = np.sqrt(c[:, None, None] ** 2 + c[None, :, None] ** 2 + c[None, None, :] ** 2)
-    g = (1.0 / (1.0 + r / 400.0)).astype(np.float32)
-    run_sweeps("cfg1", rj, 0.05, 20, growth=g)
+    return (1.0 / (1.0 + r / 400.0)).astype(np.float32)
+
+
+@pytest.mark.parametrize("name,with_growth", [("tiny8x2", False), ("cfg1", False), ("cfg1", True),
+                                              (64, False), ("paper15s", False),
+                                              ("paper15s", True)])
+def test_library_coefficients_match_oracle(name, with_growth):
+    """alpha, beta from the library's coefficient pass, which loads R^l and N^l only
+    for 4-voxel groups inside the survey support, against the oracle's per-voxel sums:
+    exact zeros wherever every R^l = 0, float32 rounding elsewhere.  The 15
+    magnitude-binned subsamples (each with its own R^l) take two unrolled chunks of
+    eight in the pass."""
+    mk = case_mock(name)
+    g = radial_growth(mk) if with_growth else None
+    s = Sampler([chain_spec(mk, growth=g)])
+    st = s.state(0)
+    a, b, _ = model.coefficients(mk["R"], mk["counts"], mk["bias"], mk["nbar"],
+                                 None if g is None else g.astype(np.float64))
+    outside = ~(np.asarray(mk["R"]) > 0).any(axis=0)
+    print(f"{name} growth={with_growth}: {outside.mean():.3f} of the voxels outside the support")
+    assert 0 < outside.sum() < outside.size
+    assert np.all(st["alpha"][outside] == 0) and np.all(st["beta"][outside] == 0)
+    inside = ~outside
+    np.testing.assert_allclose(st["alpha"][inside], a[inside], rtol=1e-5, atol=0)
+    scale = np.abs(b[inside]).max()
+    np.testing.assert_allclose(st["beta"][inside], b[inside], rtol=1e-5, atol=1e-5 * scale)
+    s.close()
 
 
 def run_sweeps(name, rj, eps, nsteps, alpha_prior=1.0, growth=None):
