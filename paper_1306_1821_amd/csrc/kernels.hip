@@ -899,17 +899,39 @@ __device__ __forceinline__ void zpass_t(const ChainDev& d, int lt, const ZArgs a
       v[e] = gldi(reinterpret_cast<const float2*>(a.src), ro + t + T * e);
   } else {  // Z_NOISE: white noise w_i from Philox stream 3 (11: warm start), element = voxel index
     const uint32_t stream = (a.flags & ZF_WARM) ? hmcrng::kWarm : hmcrng::kMomenta;
+    if constexpr (T % 2 == 0 && E % 2 == 0) {
+      // One Philox block covers 4 voxels: words 0, 1 go to the voxel pair of lane t
+      // (t even) and words 2, 3 to that of lane t + 1.  For each element pair
+      // (e, e + E/2) the even lane computes the block of e, the odd lane that of
+      // e + E/2, and each hands its partner the two words the partner needs.
+      const bool odd = t & 1;
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const uint64_t vox = rbase + 2 * (uint64_t)(t + T * e);
-      const hmcrng::U4 w = hmcrng::block(d.seed, d.chain, stream, *d.draw, 0,
-                                         (uint32_t)(vox >> 2));
-      double z0, z1;
-      if (((vox >> 1) & 1) == 0)
-        hmcrng::box_muller(w.w[0], w.w[1], &z0, &z1);
-      else
-        hmcrng::box_muller(w.w[2], w.w[3], &z0, &z1);
-      v[e] = make_float2((float)z0, (float)z1);
+      for (int e = 0; e < E / 2; ++e) {
+        const uint64_t vox = rbase + 2 * (uint64_t)(t + T * (odd ? e + E / 2 : e));
+        const hmcrng::U4 w = hmcrng::block(d.seed, d.chain, stream, *d.draw, 0,
+                                           (uint32_t)(vox >> 2));
+        const uint32_t own0 = odd ? w.w[2] : w.w[0], own1 = odd ? w.w[3] : w.w[1];
+        const uint32_t r0 = __shfl_xor(odd ? w.w[0] : w.w[2], 1);
+        const uint32_t r1 = __shfl_xor(odd ? w.w[1] : w.w[3], 1);
+        double z0, z1;
+        hmcrng::box_muller(odd ? r0 : own0, odd ? r1 : own1, &z0, &z1);
+        v[e] = make_float2((float)z0, (float)z1);
+        hmcrng::box_muller(odd ? own0 : r0, odd ? own1 : r1, &z0, &z1);
+        v[e + E / 2] = make_float2((float)z0, (float)z1);
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const uint64_t vox = rbase + 2 * (uint64_t)(t + T * e);
+        const hmcrng::U4 w = hmcrng::block(d.seed, d.chain, stream, *d.draw, 0,
+                                           (uint32_t)(vox >> 2));
+        double z0, z1;
+        if (((vox >> 1) & 1) == 0)
+          hmcrng::box_muller(w.w[0], w.w[1], &z0, &z1);
+        else
+          hmcrng::box_muller(w.w[2], w.w[3], &z0, &z1);
+        v[e] = make_float2((float)z0, (float)z1);
+      }
     }
   }
 
