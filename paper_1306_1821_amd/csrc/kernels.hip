@@ -1781,22 +1781,26 @@ __global__ void __launch_bounds__(kThreads) k_energy_k(const ChainDev* __restric
 
 // shell sums sigma_m and mode counts n_m (full-grid weights) per tile
 // Per-shell sums over k-space tiles into shpart[tile][m] (weights w = 1 on the
-// kz = 0, N/2 planes, 2 elsewhere; k = 0 excluded), one bin copy per wave; the
+// kz = 0, N/2 planes, 2 elsewhere; k = 0 excluded) through per-wave LDS bins; the
 // shell index comes from the branch-free integer rule (no table loads):
 //   SP_POWER: sum w |delta_hat|^2 (sigma_m), with counts also sum w (mode counts,
 //             into mpart; init only, the sweep's P draw needs sigma alone);
 //   SP_DOT:   sum w Re(conj(delta_hat) g_hat) of the stored state and gradient
 //             (the joint move's dU at its start).
 enum ShellSum : int { SP_POWER = 0, SP_DOT = 1 };
+constexpr int kSumThreads = 1024;
 template <int WHAT>
-__global__ void __launch_bounds__(kThreads) k_shell_sum(const ChainDev* __restrict__ ch,
-                                                         int nch, int total, int with_counts) {
-  __shared__ double bins[4 * kMaxBins];
-  __shared__ double cnt[4 * kMaxBins];
+__global__ void __launch_bounds__(kSumThreads) k_shell_sum(const ChainDev* __restrict__ ch,
+                                                            int nch, int total, int with_counts) {
+  // one bin copy per wave; 1024-thread blocks keep 16 waves per tile in flight
+  // (the per-mode work is a dependent chain of index arithmetic, not bandwidth)
+  constexpr int kWaves = kSumThreads / 64;
+  __shared__ double bins[kWaves * kMaxBins];
+  __shared__ double cnt[kWaves * kMaxBins];
   for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
     const ChainDev& d = ch[find_chain(ch, nch, tile, kTileK)];
     const int lt = tile - d.tb[kTileK];
-    for (int i = threadIdx.x; i < 4 * kMaxBins; i += kThreads) {
+    for (int i = threadIdx.x; i < kWaves * kMaxBins; i += kSumThreads) {
       bins[i] = 0.0;
       cnt[i] = 0.0;
     }
@@ -1804,7 +1808,7 @@ __global__ void __launch_bounds__(kThreads) k_shell_sum(const ChainDev* __restri
     const int wv = (threadIdx.x >> 6) * kMaxBins;
     const uint32_t qmax = 3u * (uint32_t)(d.n / 2) * (uint32_t)(d.n / 2), nbu = (uint32_t)d.nb;
     const float inv_qmax = 1.f / (float)qmax;
-    for (int j = threadIdx.x; j < kElemPerTile; j += kThreads) {
+    for (int j = threadIdx.x; j < kElemPerTile; j += kSumThreads) {
       const long long i = (long long)lt * kElemPerTile + j;
       if (i >= d.nh) break;
       int fx, fy, kz;
@@ -1824,12 +1828,15 @@ __global__ void __launch_bounds__(kThreads) k_shell_sum(const ChainDev* __restri
       if (WHAT == SP_POWER && with_counts) atomicAdd(&cnt[wv + m], w);
     }
     __syncthreads();
-    for (int m = threadIdx.x; m < d.nb; m += kThreads) {
-      d.shpart[(size_t)lt * d.nb + m] =
-          ((bins[m] + bins[kMaxBins + m]) + bins[2 * kMaxBins + m]) + bins[3 * kMaxBins + m];
-      if (WHAT == SP_POWER && with_counts)
-        d.mpart[(size_t)lt * d.nb + m] =
-            ((cnt[m] + cnt[kMaxBins + m]) + cnt[2 * kMaxBins + m]) + cnt[3 * kMaxBins + m];
+    for (int m = threadIdx.x; m < d.nb; m += kSumThreads) {
+      double sb = 0.0, sc = 0.0;
+#pragma unroll
+      for (int c = 0; c < kWaves; ++c) {  // fixed order: reproducible
+        sb += bins[c * kMaxBins + m];
+        sc += cnt[c * kMaxBins + m];
+      }
+      d.shpart[(size_t)lt * d.nb + m] = sb;
+      if (WHAT == SP_POWER && with_counts) d.mpart[(size_t)lt * d.nb + m] = sc;
     }
     __syncthreads();
   }
@@ -2242,11 +2249,12 @@ void launch_energy_r(const ChainDev* ch, int nch, int total, hipStream_t s) {
   hipLaunchKernelGGL(k_energy_r, dim3(eg(total)), dim3(kThreads), 0, s, ch, nch, total);
 }
 void launch_shell_power(const ChainDev* ch, int nch, int total, hipStream_t s, int with_counts) {
-  hipLaunchKernelGGL(k_shell_sum<SP_POWER>, dim3(eg(total)), dim3(kThreads), 0, s, ch, nch, total,
-                     with_counts);
+  hipLaunchKernelGGL(k_shell_sum<SP_POWER>, dim3(eg(total)), dim3(kSumThreads), 0, s, ch, nch,
+                     total, with_counts);
 }
 void launch_shell_dot(const ChainDev* ch, int nch, int total, hipStream_t s) {
-  hipLaunchKernelGGL(k_shell_sum<SP_DOT>, dim3(eg(total)), dim3(kThreads), 0, s, ch, nch, total, 0);
+  hipLaunchKernelGGL(k_shell_sum<SP_DOT>, dim3(eg(total)), dim3(kSumThreads), 0, s, ch, nch, total,
+                     0);
 }
 void launch_shell_index(const ChainDev* ch, int total, int16_t* out, hipStream_t s) {
   hipLaunchKernelGGL(k_shell_index, dim3(eg(total)), dim3(kThreads), 0, s, ch, total, out);
