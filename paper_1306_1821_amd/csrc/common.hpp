@@ -7,7 +7,7 @@
 
 namespace hmc {
 
-constexpr int kThreads = 256;     // block size of every kernel but the k-space shell sums (1024)
+constexpr int kThreads = 256;     // block size of the passes (a few elementwise kernels use 1024)
 constexpr int kMaxBins = 128;
 constexpr int kMaxSub = 32;
 constexpr int kElemPerTile = 16384;  // elementwise kernels: elements per tile

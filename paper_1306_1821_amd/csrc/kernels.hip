@@ -507,6 +507,10 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Block size of the elementwise passes whose per-element work is a short dependent
+// chain (shell sums, coefficients, accept / reject copies): 16 waves per tile in flight.
+constexpr int kWideThreads = 1024;
+
 // Deterministic block sum (fixed butterfly tree per wave, fixed wave order).
 __device__ __forceinline__ double block_sum(double v, double* red) {
   v = wave_sum(v);
@@ -515,6 +519,17 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   if ((threadIdx.x & 63) == 0) red[w] = v;
   __syncthreads();
   return red[0] + red[1] + red[2] + red[3];
+}
+template <int W>  // the same for blocks of W waves
+__device__ __forceinline__ double block_sum_w(double v, double* red) {
+  v = wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int w = 0; w < W; ++w) s += red[w];
+  return s;
 }
 
 // Shell bins of the k-space dot pass in LDS: kBinCopies copies per wave,
@@ -1552,9 +1567,9 @@ __device__ __forceinline__ bool observed(const ChainDev& d, uint32_t i4) {
   return HMC_OBSMASK == 0 || ((d.obs[i4 >> 6] >> (i4 & 63)) & 1ull);
 }
 
-__global__ void __launch_bounds__(kThreads) k_coeff(const ChainDev* __restrict__ ch, int nch,
-                                                     int total) {
-  __shared__ double red[4];
+__global__ void __launch_bounds__(kWideThreads) k_coeff(const ChainDev* __restrict__ ch,
+                                                         int nch, int total) {
+  __shared__ double red[kWideThreads / 64];
   __shared__ float cb2n[kMaxSub], cb[kMaxSub], cn[kMaxSub];
   for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
     const ChainDev& d = ch[find_chain(ch, nch, tile, kTileR)];
@@ -1568,7 +1583,7 @@ __global__ void __launch_bounds__(kThreads) k_coeff(const ChainDev* __restrict__
     __syncthreads();
     const uint32_t nv4 = (uint32_t)(d.nv / 4), base4 = (uint32_t)lt * (kElemPerTile / 4);
     double acc = 0.0;
-    for (uint32_t j = threadIdx.x; j < kElemPerTile / 4; j += kThreads) {
+    for (uint32_t j = threadIdx.x; j < kElemPerTile / 4; j += kWideThreads) {
       const uint32_t i4 = base4 + j;
       if (i4 >= nv4) break;
       f4v al = {0.f, 0.f, 0.f, 0.f}, be = {0.f, 0.f, 0.f, 0.f};
@@ -1602,7 +1617,7 @@ __global__ void __launch_bounds__(kThreads) k_coeff(const ChainDev* __restrict__
       gst4(d.beta, i4, be);
       acc += (double)al[0] + (double)al[1] + (double)al[2] + (double)al[3];
     }
-    const double s = block_sum(acc, red);
+    const double s = block_sum_w<kWideThreads / 64>(acc, red);
     if (threadIdx.x == 0) d.part[kPartAlpha * d.maxtiles + lt] = s;
     __syncthreads();
   }
@@ -1788,19 +1803,18 @@ __global__ void __launch_bounds__(kThreads) k_energy_k(const ChainDev* __restric
 //   SP_DOT:   sum w Re(conj(delta_hat) g_hat) of the stored state and gradient
 //             (the joint move's dU at its start).
 enum ShellSum : int { SP_POWER = 0, SP_DOT = 1 };
-constexpr int kSumThreads = 1024;
 template <int WHAT>
-__global__ void __launch_bounds__(kSumThreads) k_shell_sum(const ChainDev* __restrict__ ch,
+__global__ void __launch_bounds__(kWideThreads) k_shell_sum(const ChainDev* __restrict__ ch,
                                                             int nch, int total, int with_counts) {
   // one bin copy per wave; 1024-thread blocks keep 16 waves per tile in flight
   // (the per-mode work is a dependent chain of index arithmetic, not bandwidth)
-  constexpr int kWaves = kSumThreads / 64;
+  constexpr int kWaves = kWideThreads / 64;
   __shared__ double bins[kWaves * kMaxBins];
   __shared__ double cnt[kWaves * kMaxBins];
   for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
     const ChainDev& d = ch[find_chain(ch, nch, tile, kTileK)];
     const int lt = tile - d.tb[kTileK];
-    for (int i = threadIdx.x; i < kWaves * kMaxBins; i += kSumThreads) {
+    for (int i = threadIdx.x; i < kWaves * kMaxBins; i += kWideThreads) {
       bins[i] = 0.0;
       cnt[i] = 0.0;
     }
@@ -1808,7 +1822,7 @@ __global__ void __launch_bounds__(kSumThreads) k_shell_sum(const ChainDev* __res
     const int wv = (threadIdx.x >> 6) * kMaxBins;
     const uint32_t qmax = 3u * (uint32_t)(d.n / 2) * (uint32_t)(d.n / 2), nbu = (uint32_t)d.nb;
     const float inv_qmax = 1.f / (float)qmax;
-    for (int j = threadIdx.x; j < kElemPerTile; j += kSumThreads) {
+    for (int j = threadIdx.x; j < kElemPerTile; j += kWideThreads) {
       const long long i = (long long)lt * kElemPerTile + j;
       if (i >= d.nh) break;
       int fx, fy, kz;
@@ -1828,7 +1842,7 @@ __global__ void __launch_bounds__(kSumThreads) k_shell_sum(const ChainDev* __res
       if (WHAT == SP_POWER && with_counts) atomicAdd(&cnt[wv + m], w);
     }
     __syncthreads();
-    for (int m = threadIdx.x; m < d.nb; m += kSumThreads) {
+    for (int m = threadIdx.x; m < d.nb; m += kWideThreads) {
       double sb = 0.0, sc = 0.0;
 #pragma unroll
       for (int c = 0; c < kWaves; ++c) {  // fixed order: reproducible
@@ -1859,8 +1873,8 @@ __global__ void __launch_bounds__(kThreads) k_shell_index(const ChainDev* __rest
 // delta_hat per shell and take the move's g_hat and real field.
 // k-space arrays move two complex entries (16 bytes) per access: N^2 (N/2 + 1)
 // and the tile size are even
-__global__ void __launch_bounds__(kThreads) k_commit_k(const ChainDev* __restrict__ ch, int nch,
-                                                        int total, int what) {
+__global__ void __launch_bounds__(kWideThreads) k_commit_k(const ChainDev* __restrict__ ch,
+                                                            int nch, int total, int what) {
   for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
     const ChainDev& d = ch[find_chain(ch, nch, tile, kTileK)];
     const int lt = tile - d.tb[kTileK];
@@ -1870,7 +1884,7 @@ __global__ void __launch_bounds__(kThreads) k_commit_k(const ChainDev* __restric
     const uint32_t nh2 = (uint32_t)(d.nh / 2), base2 = (uint32_t)lt * (kElemPerTile / 2);
     float* dk = (float*)d.dk;
     float* gk = (float*)d.gk;
-    for (uint32_t j = threadIdx.x; j < kElemPerTile / 2; j += kThreads) {
+    for (uint32_t j = threadIdx.x; j < kElemPerTile / 2; j += kWideThreads) {
       const uint32_t i2 = base2 + j;
       if (i2 >= nh2) break;
       gst4(gk, i2, gld4((const float*)d.bgk, i2));
@@ -1892,15 +1906,15 @@ __global__ void __launch_bounds__(kThreads) k_commit_k(const ChainDev* __restric
     }
   }
 }
-__global__ void __launch_bounds__(kThreads) k_commit_r(const ChainDev* __restrict__ ch, int nch,
-                                                        int total, int what) {
+__global__ void __launch_bounds__(kWideThreads) k_commit_r(const ChainDev* __restrict__ ch,
+                                                            int nch, int total, int what) {
   for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
     const ChainDev& d = ch[find_chain(ch, nch, tile, kTileR)];
     const int lt = tile - d.tb[kTileR];
     const bool acc = what == C_HMC ? d.P[kAcc] != 0.0 : d.P[kRjAcc] != 0.0;
     if (!acc) continue;
     const uint32_t nv4 = (uint32_t)(d.nv / 4), base4 = (uint32_t)lt * (kElemPerTile / 4);
-    for (uint32_t j = threadIdx.x; j < kElemPerTile / 4; j += kThreads) {
+    for (uint32_t j = threadIdx.x; j < kElemPerTile / 4; j += kWideThreads) {
       const uint32_t i4 = base4 + j;
       if (i4 >= nv4) break;
       gst4(d.dr, i4, gld4(d.drn, i4));
@@ -2228,7 +2242,7 @@ void launch_warm_combine(const ChainDev* ch, int total_r, const float* mu, const
                      logvar);
 }
 void launch_coeff(const ChainDev* ch, int nch, int total, hipStream_t s) {
-  hipLaunchKernelGGL(k_coeff, dim3(eg(total)), dim3(kThreads), 0, s, ch, nch, total);
+  hipLaunchKernelGGL(k_coeff, dim3(eg(total)), dim3(kWideThreads), 0, s, ch, nch, total);
 }
 void launch_alpha_sum(const ChainDev* ch, int nch, int total, hipStream_t s) {
   hipLaunchKernelGGL(k_alpha_sum, dim3(eg(total)), dim3(kThreads), 0, s, ch, nch, total);
@@ -2249,11 +2263,11 @@ void launch_energy_r(const ChainDev* ch, int nch, int total, hipStream_t s) {
   hipLaunchKernelGGL(k_energy_r, dim3(eg(total)), dim3(kThreads), 0, s, ch, nch, total);
 }
 void launch_shell_power(const ChainDev* ch, int nch, int total, hipStream_t s, int with_counts) {
-  hipLaunchKernelGGL(k_shell_sum<SP_POWER>, dim3(eg(total)), dim3(kSumThreads), 0, s, ch, nch,
+  hipLaunchKernelGGL(k_shell_sum<SP_POWER>, dim3(eg(total)), dim3(kWideThreads), 0, s, ch, nch,
                      total, with_counts);
 }
 void launch_shell_dot(const ChainDev* ch, int nch, int total, hipStream_t s) {
-  hipLaunchKernelGGL(k_shell_sum<SP_DOT>, dim3(eg(total)), dim3(kSumThreads), 0, s, ch, nch, total,
+  hipLaunchKernelGGL(k_shell_sum<SP_DOT>, dim3(eg(total)), dim3(kWideThreads), 0, s, ch, nch, total,
                      0);
 }
 void launch_shell_index(const ChainDev* ch, int total, int16_t* out, hipStream_t s) {
@@ -2261,9 +2275,9 @@ void launch_shell_index(const ChainDev* ch, int total, int16_t* out, hipStream_t
 }
 void launch_commit(int what, const ChainDev* ch, int nch, int total_k, int total_r,
                    hipStream_t s) {
-  hipLaunchKernelGGL(k_commit_k, dim3(eg(total_k)), dim3(kThreads), 0, s, ch, nch, total_k,
+  hipLaunchKernelGGL(k_commit_k, dim3(eg(total_k)), dim3(kWideThreads), 0, s, ch, nch, total_k,
                      what);
-  hipLaunchKernelGGL(k_commit_r, dim3(eg(total_r)), dim3(kThreads), 0, s, ch, nch, total_r,
+  hipLaunchKernelGGL(k_commit_r, dim3(eg(total_r)), dim3(kWideThreads), 0, s, ch, nch, total_r,
                      what);
 }
 void launch_copy_real(const ChainDev* ch, int total_r, const float* src, float* dst,
