@@ -87,7 +87,7 @@ struct ChainDev {
   float2* bgk;
   float* drn;
   double* part;    // [kPartSlots][maxtiles]
-  double* shpart;  // [maxtiles][nb]
+  double* shpart;  // [nb][maxtiles]: per-shell partial sums of each tile
   double* mpart;   // [maxtiles][3 * nsub]
   // library-owned small device state
   double* P;       // parameter block (kPSize doubles)

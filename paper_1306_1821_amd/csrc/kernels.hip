@@ -569,13 +569,13 @@ __device__ __forceinline__ void bins_zero(B* bins) {
   __syncthreads();
 }
 template <class B>
-__device__ __forceinline__ void bins_flush(B* bins, double* dst, int nb) {
+__device__ __forceinline__ void bins_flush(B* bins, double* dst, int nb, int stride) {
   __syncthreads();
   for (int m = threadIdx.x; m < nb; m += kThreads) {
     double s = 0.0;
 #pragma unroll
     for (int i = 0; i < 4 * kBinCopies; ++i) s += (double)bins[i * kBinStride + m];
-    dst[m] = s;
+    dst[(size_t)m * stride] = s;
   }
   __syncthreads();
 }
@@ -760,7 +760,7 @@ __device__ __forceinline__ void xpass(const ChainDev& d, int lt, const XArgs a, 
       d.part[kPartPri * d.maxtiles + lt] = s1;
     }
   }
-  if (dot) bins_flush(bins, d.shpart + (size_t)lt * d.nb, d.nb);
+  if (dot) bins_flush(bins, d.shpart + lt, d.nb, d.maxtiles);
   __syncthreads();
 }
 
@@ -1795,7 +1795,7 @@ __global__ void __launch_bounds__(kThreads) k_energy_k(const ChainDev* __restric
 }
 
 // shell sums sigma_m and mode counts n_m (full-grid weights) per tile
-// Per-shell sums over k-space tiles into shpart[tile][m] (weights w = 1 on the
+// Per-shell sums over k-space tiles into shpart[m][tile] (weights w = 1 on the
 // kz = 0, N/2 planes, 2 elsewhere; k = 0 excluded) through per-wave LDS bins; the
 // shell index comes from the branch-free integer rule (no table loads):
 //   SP_POWER: sum w |delta_hat|^2 (sigma_m), with counts also sum w (mode counts,
@@ -1849,7 +1849,7 @@ __global__ void __launch_bounds__(kWideThreads) k_shell_sum(const ChainDev* __re
         sb += bins[c * kMaxBins + m];
         sc += cnt[c * kMaxBins + m];
       }
-      d.shpart[(size_t)lt * d.nb + m] = sb;
+      d.shpart[(size_t)m * d.maxtiles + lt] = sb;
       if (WHAT == SP_POWER && with_counts) d.mpart[(size_t)lt * d.nb + m] = sc;
     }
     __syncthreads();
@@ -1945,8 +1945,9 @@ __global__ void __launch_bounds__(kThreads) k_reduce_slot(const ChainDev* __rest
   if (threadIdx.x == 0) d.P[dst] = mean ? s / (double)d.nv : s;
 }
 
-// Column sums of a per-tile partial matrix [tiles][width], one block per
-// (column, chain), fixed order (strided per thread, then the block tree).
+// Column sums of per-tile partials (src 0: shpart [shell][tile]; src 1: mpart
+// [tile][width]), one block per (column, chain), fixed order (strided per thread,
+// then the block tree).
 // mode 0: P[dst + q] = sum (per-shell tables, width nb)
 // mode 1: P[dst + (q % 3) * kMaxSub + q / 3] = sum (moments, width 3 nsub)
 // mode 2: P[dst + q] = sum / 2 + (alpha_prior - 1) (joint-move dU, width nb)
@@ -1957,9 +1958,13 @@ __global__ void __launch_bounds__(kThreads) k_colsum(const ChainDev* __restrict_
   const int q = blockIdx.x;
   const int width = mode == 1 ? 3 * d.nsub : d.nb;
   if (q >= width) return;
-  const double* p = src == 0 ? d.shpart : d.mpart;
   double acc = 0.0;
-  for (int t = threadIdx.x; t < d.nt[cls]; t += kThreads) acc += p[(size_t)t * width + q];
+  if (src == 0) {  // shell partials, [shell][tile]: a block reads one contiguous row
+    const double* p = d.shpart + (size_t)q * d.maxtiles;
+    for (int t = threadIdx.x; t < d.nt[cls]; t += kThreads) acc += p[t];
+  } else {
+    for (int t = threadIdx.x; t < d.nt[cls]; t += kThreads) acc += d.mpart[(size_t)t * width + q];
+  }
   const double s = block_sum(acc, red);
   if (threadIdx.x == 0) {
     if (mode == 0) d.P[dst + q] = s;
