@@ -514,6 +514,18 @@ def main():
     for i in range(3):
         s.trajectory(20_000 + i)
     ms_all, launches_all = s.timing(0)
+    # per-trajectory device time: HIP events around each of 100 trajectories
+    # enqueued through the asynchronous entry point (no host wait in between)
+    dH_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+    acc_dev = torch.zeros(1, dtype=torch.int32, device="cuda")
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(100)]
+    for i, (ea, eb) in enumerate(evs):
+        ea.record()
+        s.trajectory_async(30_000 + i, dH_dev, acc_dev)
+        eb.record()
+    torch.cuda.synchronize()
+    traj_ms = float(np.median([ea.elapsed_time(eb) for ea, eb in evs]))
 
     steps = args.steps * spec["nsteps"]
     value = steps / dt
@@ -546,6 +558,9 @@ def main():
         "acceptance": float(np.mean(acc)),
         "rj_acceptance": float(np.mean(rj_acc)),
         "trajectory_leapfrog_steps_per_s": ntraj * spec["nsteps"] / dt_traj,
+        "trajectory_median": {"ms": traj_ms, "leapfrog_steps_per_s": spec["nsteps"] / (1e-3 * traj_ms),
+                              "trajectories": len(evs),
+                              "timing": "HIP events around each trajectory, asynchronous entry point"},
         "pass_ms_per_step": {"kspace": ms_all[0] / max(1, launches_all[0]),
                              "ypass": ms_all[1] / max(1, launches_all[1]),
                              "zpass": ms_all[2] / max(1, launches_all[2])},
