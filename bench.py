@@ -565,6 +565,16 @@ def main():
                              "ypass": ms_all[1] / max(1, launches_all[1]),
                              "zpass": ms_all[2] / max(1, launches_all[2])},
     }
+    # the whole step (x + 2 y + z passes, HIP events) against two byte counts: the
+    # fused four-pass design's 56 N^3 bytes and the 40 N^3 bytes of a step whose two
+    # FFTs take the minimum two passes each over a grid larger than on-chip memory
+    step_ms = (out["pass_ms_per_step"]["kspace"] + 2 * out["pass_ms_per_step"]["ypass"]
+               + out["pass_ms_per_step"]["zpass"])
+    nv = n ** 3
+    out["step_roofline"] = {
+        "ms": step_ms, "bytes_fused_design": 56 * nv, "bytes_lower_bound": 40 * nv,
+        "frac_fused_design": 56 * nv / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "frac_lower_bound": 40 * nv / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
     s.close()
     del s
     torch.cuda.empty_cache()
