@@ -63,12 +63,24 @@ def test_joint_move_energy_error_second_order():
 
 @pytest.mark.slow
 def test_joint_move_preserves_power_posterior():
-    """Chains {delta-HMC + inverse-Gamma P} and {delta-HMC + joint move} agree on P (proper prior)."""
+    """Chains {delta-HMC + inverse-Gamma P} and {delta-HMC + joint move} agree on P.
+
+    With a proper prior (alpha = 0) both kernels leave the joint posterior of
+    (delta, P) invariant (eq. INVERSE_GAMMA and Appendix C's
+    eq. spec_posterior_MIXING_1), so the marginal of ln P per shell must be the
+    same.  6000 sweeps per arm: a joint move whose HMC mass follows theta, the
+    variable it moves, shifts the mean of ln P on the first shell by half a
+    posterior standard deviation (about 6.7 ESS-based standard errors here),
+    which the 4-standard-error window catches.  The variance ratio is checked on
+    the two data-dominated shells only: the noise-dominated ones have rare long
+    excursions into low P that make their variance estimate unreliable at this
+    length (their means are still compared).
+    """
     mk, cfg, post0, lam0, dk0, rcfg = setup(alpha_prior=0.0)
     nm = grid.mode_counts(cfg.n, cfg.nb)
     n, box, nb = cfg.n, cfg.box, cfg.nb
 
-    def run(use_rj, nsweep=1500):
+    def run(use_rj, nsweep=6000):
         dk, lam = dk0.copy(), lam0.copy()
         out = []
         for s in range(nsweep):
@@ -89,5 +101,6 @@ def test_joint_move_preserves_power_posterior():
     for m in range(nb):
         ea, eb = _ess(a[:, m]), _ess(b[:, m])
         se = np.sqrt(a[:, m].var() / ea + b[:, m].var() / eb)
-        assert abs(a[:, m].mean() - b[:, m].mean()) < 5 * se, m
-        assert 0.6 < b[:, m].var() / a[:, m].var() < 1.6, m
+        assert abs(a[:, m].mean() - b[:, m].mean()) < 4 * se, (m, (b[:, m].mean() - a[:, m].mean()) / se)
+    for m in (0, 1):
+        assert 0.75 < b[:, m].var() / a[:, m].var() < 1.33, m
