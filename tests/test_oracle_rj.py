@@ -50,6 +50,35 @@ def test_reflection_keeps_bounds_and_flips_momentum():
     assert np.allclose(th, [0.5, 1.5, -0.3]) and np.allclose(rho, [1.0, -1.0, 1.0])
 
 
+def test_joint_move_runs_backwards_to_its_start():
+    """Detailed balance needs a reversible map: from the proposal's end point with
+    the momentum negated, the move (same mass, same integrator) returns to the
+    start, and its energy error is the negative of the forward one."""
+    mk, cfg, post, lam, dk, rcfg = setup()
+    nm = grid.mode_counts(cfg.n, cfg.nb)
+    r = dict(rcfg, eps=0.15, nsteps=12)
+    fwd = rj.joint_move(dk, lam, post, nm, r, 3)
+    assert np.max(np.abs(fwd["theta"] - np.log(lam))) > 0.05      # the move went somewhere
+    back = rj.joint_move(fwd["dk_prop"], np.exp(fwd["theta"]), post, nm, r, 3, rho0=-fwd["rho"])
+    assert np.allclose(back["mass"], fwd["mass"], rtol=0, atol=0)
+    assert np.max(np.abs(back["theta"] - np.log(lam))) < 1e-10
+    assert abs(back["dH"] + fwd["dH"]) < 1e-8 * max(1.0, abs(fwd["H0"]))
+    dkb = back["dk_prop"]
+    assert np.max(np.abs(dkb - dk)) < 1e-10 * np.max(np.abs(dk))
+
+
+def test_joint_move_reports_wall_hits():
+    """Walls one step away are hit and counted; distant walls are not."""
+    mk, cfg, post, lam, dk, rcfg = setup()
+    nm = grid.mode_counts(cfg.n, cfg.nb)
+    far = rj.joint_move(dk, lam, post, nm, rcfg, 5)
+    assert far["wall_hits"] == 0
+    near = rj.joint_move(dk, lam, post, nm, dict(rcfg, lam_lo=lam * np.exp(-0.05),
+                                                 lam_hi=lam * np.exp(0.05)), 5)
+    assert near["wall_hits"] > 0
+    assert np.all(np.abs(near["theta"] - np.log(lam)) <= 0.05 + 1e-12)
+
+
 def test_joint_move_energy_error_second_order():
     mk, cfg, post, lam, dk, rcfg = setup()
     nm = grid.mode_counts(cfg.n, cfg.nb)
