@@ -114,6 +114,9 @@ typedef struct hmc_sweep_stats {
   int32_t accepted;      /* 1 if the density trajectory was accepted */
   double rj_dH;          /* energy error of the joint move (0 if off) */
   int32_t rj_accepted;   /* 1 if the joint move was accepted */
+  int32_t rj_wall_hits;  /* reflections of ln lambda off the joint move's walls
+                            (rj_log_bound) during the move; 0 when the walls were
+                            never reached */
   const double* pk;      /* [n_bins] P_m after the sweep, (Mpc/h)^3 */
   const double* bias;    /* [c] */
   const double* nbar;    /* [c] */
@@ -181,8 +184,8 @@ hmc_status gibbs_sweep(hmc_ctx* ctx, uint64_t sweep_index, hmc_sweep_stats* out)
 
 /* Doubles of the per-sweep record gibbs_sweep_async writes, summed over chains:
  * for each chain, in order, [dH, accepted (0/1), rj_dH, rj_accepted, status
- * (0 ok, nonzero: a draw or energy was not finite), P_m (n_bins values,
- * (Mpc/h)^3), b_l (c values), Nbar_l (c values)]. */
+ * (0 ok, nonzero: a draw or energy was not finite), rj_wall_hits, P_m (n_bins
+ * values, (Mpc/h)^3), b_l (c values), Nbar_l (c values)]. */
 size_t hmc_sweep_record_doubles(const hmc_ctx* ctx);
 
 /* gibbs_sweep without a host round trip: stats_dev (device float64,

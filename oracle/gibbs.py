@@ -203,11 +203,12 @@ def sweep(state, data, cfg, s):
     sigma = grid.shell_sums(dk, nb)
     lam = model.lambdas(pk, n, box)
     lam = draw_power(sigma, n_modes, lam, cfg["alpha_prior"], cfg["seed"], cfg["chain"], s)
-    out = dict(dH=tr["dH"], accepted=tr["accepted"], sigma=sigma)
+    out = dict(dH=tr["dH"], accepted=tr["accepted"], log_u=tr["log_u"], sigma=sigma)
     if cfg.get("rj", False):
         jm = rj.joint_move(dk, lam, post, n_modes, cfg, s)
         dk, lam = jm["dk"], jm["lam"]
-        out.update(rj_dH=jm["dH"], rj_accepted=jm["accepted"])
+        out.update(rj_dH=jm["dH"], rj_accepted=jm["accepted"], rj_wall_hits=jm["wall_hits"],
+                   rj_log_u=jm["log_u"])
     delta = grid.inv(dk, n)
     stat = static_moments(R, counts)
     mom = delta_moments(delta if growth is None else np.asarray(growth, np.float64) * delta, R, counts)

@@ -36,6 +36,7 @@ class HmcBuffers(ctypes.Structure):
 class HmcSweepStats(ctypes.Structure):
     _fields_ = [("dH", ctypes.c_double), ("accepted", ctypes.c_int32),
                 ("rj_dH", ctypes.c_double), ("rj_accepted", ctypes.c_int32),
+                ("rj_wall_hits", ctypes.c_int32),
                 ("pk", ctypes.POINTER(ctypes.c_double)),
                 ("bias", ctypes.POINTER(ctypes.c_double)),
                 ("nbar", ctypes.POINTER(ctypes.c_double))]
@@ -266,7 +267,7 @@ class Sampler:
         for i, c in enumerate(self.chains):
             s = st[i]
             out.append(dict(dH=s.dH, accepted=bool(s.accepted), rj_dH=s.rj_dH,
-                            rj_accepted=bool(s.rj_accepted),
+                            rj_accepted=bool(s.rj_accepted), rj_wall_hits=int(s.rj_wall_hits),
                             pk=np.array(s.pk[:c["nb"]]), bias=np.array(s.bias[:c["nsub"]]),
                             nbar=np.array(s.nbar[:c["nsub"]])))
         return out

@@ -10,6 +10,9 @@ namespace hmc {
 constexpr int kThreads = 256;     // block size of the passes (a few elementwise kernels use 1024)
 constexpr int kMaxBins = 128;
 constexpr int kMaxSub = 32;
+// doubles ahead of P_m in each chain's sweep record (dH, accepted, rj_dH,
+// rj_accepted, status, rj_wall_hits)
+constexpr int kRecHead = 6;
 constexpr int kElemPerTile = 16384;  // elementwise kernels: elements per tile
 
 // tile classes (index into ChainDev::tb)
@@ -28,6 +31,7 @@ enum POff : int {
   kDH = 6, kAcc = 7, kAbar = 8, kLogU = 9,
   kRjDH = 10, kRjAcc = 11, kRjU0 = 12, kRjK0 = 13, kStatus = 14, kDnew = 15,
   kRjStep = 16, kHK = 17, kHP = 18, kHD = 19, kGbar = 20, kLmean = 21,
+  kRjHits = 22,  // joint move: reflections off the walls in the last move
   // arrays
   kLam = 32,                       // lambda_m (unitary), nb
   kSigma = kLam + kMaxBins,        // sigma_m, nb
@@ -38,7 +42,8 @@ enum POff : int {
   kLo = kMth + kMaxBins,
   kHi = kLo + kMaxBins,
   kDU = kHi + kMaxBins,
-  kNmodes = kDU + kMaxBins,
+  kWall = kDU + kMaxBins,          // joint move: reflections per shell in the current move
+  kNmodes = kWall + kMaxBins,
   kBias = kNmodes + kMaxBins,      // per subsample
   kNbar = kBias + kMaxSub,
   kS0 = kNbar + kMaxSub,

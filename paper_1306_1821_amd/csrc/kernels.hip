@@ -1350,8 +1350,8 @@ __global__ void __launch_bounds__(kThreads) k_shell_lut(const ChainDev* __restri
 
 // results of the last trajectory / sweep into caller device buffers (no host
 // round trip): trajectories write dH and the accept flag per chain; sweeps write
-// per chain the record [dH, accepted, rj_dH, rj_accepted, status, P_m (physical
-// units), b_l, Nbar_l], records back to back in chain order
+// per chain the record [dH, accepted, rj_dH, rj_accepted, status, rj_wall_hits,
+// P_m (physical units), b_l, Nbar_l], records back to back in chain order
 __global__ void k_export(const ChainDev* __restrict__ ch, int nch, int sweep, double* rec,
                          int32_t* acc) {
   const int i = blockIdx.x;
@@ -1365,7 +1365,7 @@ __global__ void k_export(const ChainDev* __restrict__ ch, int nch, int sweep, do
     return;
   }
   long long off = 0;
-  for (int j = 0; j < i; ++j) off += 5 + ch[j].nb + 2 * ch[j].nsub;
+  for (int j = 0; j < i; ++j) off += kRecHead + ch[j].nb + 2 * ch[j].nsub;
   double* r = rec + off;
   const double f = d.box * d.box * d.box / ((double)d.n * d.n * d.n);
   if (threadIdx.x == 0) {
@@ -1374,11 +1374,12 @@ __global__ void k_export(const ChainDev* __restrict__ ch, int nch, int sweep, do
     r[2] = d.P[kRjDH];
     r[3] = d.P[kRjAcc];
     r[4] = d.P[kStatus];
+    r[5] = d.P[kRjHits];
   }
-  for (int m = threadIdx.x; m < d.nb; m += blockDim.x) r[5 + m] = d.P[kLam + m] * f;
+  for (int m = threadIdx.x; m < d.nb; m += blockDim.x) r[kRecHead + m] = d.P[kLam + m] * f;
   for (int l = threadIdx.x; l < d.nsub; l += blockDim.x) {
-    r[5 + d.nb + l] = d.P[kBias + l];
-    r[5 + d.nb + d.nsub + l] = d.P[kNbar + l];
+    r[kRecHead + d.nb + l] = d.P[kBias + l];
+    r[kRecHead + d.nb + d.nsub + l] = d.P[kNbar + l];
   }
 }
 
@@ -2053,22 +2054,28 @@ __global__ void k_draw_nbar_bias(const ChainDev* __restrict__ ch) {
 }
 
 // Joint (P, delta) move: HMC in theta_m = ln lambda_m at fixed whitened field.
+// The mass max(1, n_m lambda_ref,m mean(alpha) / 4) takes lambda_ref at the centre
+// of the walls (the lambda the chain started from), never the current theta: the
+// move must run the same leapfrog map from either end for detailed balance.
 // BEGIN: theta0, mass, momenta (stream 8), H0, first half kick and drift.
 // STEP:  kick with dU at the current theta, drift.
 // END:   last half kick, H1, Metropolis test (stream 9), lambda update.
 // dU_m = 1/2 sum_{k in m} w Re(conj(delta_hat) g_hat) + (alpha - 1) from the tile partials.
-__device__ void rj_reflect(double* th, double* rho, double lo, double hi) {
+// Mirror th into [lo, hi], negating rho once per reflection; returns the count.
+__device__ int rj_reflect(double* th, double* rho, double lo, double hi) {
+  int hits = 0;
   for (int it = 0; it < 64; ++it) {
     if (*th > hi) {
       *th = 2.0 * hi - *th;
-      *rho = -*rho;
     } else if (*th < lo) {
       *th = 2.0 * lo - *th;
-      *rho = -*rho;
     } else {
       break;
     }
+    *rho = -*rho;
+    ++hits;
   }
+  return hits;
 }
 
 __global__ void __launch_bounds__(kThreads) k_rj(const ChainDev* __restrict__ ch, int phase) {
@@ -2084,7 +2091,8 @@ __global__ void __launch_bounds__(kThreads) k_rj(const ChainDev* __restrict__ ch
     double th = 0.0, rho = 0.0, ms = 1.0;
     if (on) {
       th = log(d.P[kLam + m]);
-      ms = fmax(1.0, 0.25 * d.P[kNmodes + m] * d.P[kLam + m] * d.P[kAbar]);
+      const double lam_ref = exp(0.5 * (d.P[kLo + m] + d.P[kHi + m]));
+      ms = fmax(1.0, 0.25 * d.P[kNmodes + m] * lam_ref * d.P[kAbar]);
       const hmcrng::U4 w = hmcrng::block(d.seed, d.chain, hmcrng::kRjMomenta, sweep, 0,
                                          (uint32_t)(m >> 2));
       double z0, z1;
@@ -2105,7 +2113,7 @@ __global__ void __launch_bounds__(kThreads) k_rj(const ChainDev* __restrict__ ch
     if (on) {
       rho -= 0.5 * eps * dU;
       th += eps * rho / ms;
-      rj_reflect(&th, &rho, d.P[kLo + m], d.P[kHi + m]);
+      d.P[kWall + m] = (double)rj_reflect(&th, &rho, d.P[kLo + m], d.P[kHi + m]);
       d.P[kTheta + m] = th;
       d.P[kRho + m] = rho;
       d.tf[kTScale + m] = (float)exp(0.5 * (th - d.P[kTheta0 + m]));
@@ -2116,7 +2124,7 @@ __global__ void __launch_bounds__(kThreads) k_rj(const ChainDev* __restrict__ ch
       const double ms = d.P[kMth + m];
       rho -= eps * dU;
       th += eps * rho / ms;
-      rj_reflect(&th, &rho, d.P[kLo + m], d.P[kHi + m]);
+      d.P[kWall + m] += (double)rj_reflect(&th, &rho, d.P[kLo + m], d.P[kHi + m]);
       d.P[kTheta + m] = th;
       d.P[kRho + m] = rho;
       d.tf[kTScale + m] = (float)exp(0.5 * (th - d.P[kTheta0 + m]));
@@ -2130,8 +2138,10 @@ __global__ void __launch_bounds__(kThreads) k_rj(const ChainDev* __restrict__ ch
     }
     const double k1 = block_sum(on ? 0.5 * rho * rho / ms : 0.0, red);
     const double st = block_sum(on ? th : 0.0, red);
+    const double hits = block_sum(on ? d.P[kWall + m] : 0.0, red);
     __shared__ int acc_s;
     if (m == 0) {
+      d.P[kRjHits] = hits;
       const double H0 = d.P[kRjK0] + d.P[kRjU0];
       const double H1 = k1 + d.P[kD1] + am1 * st;
       const double dH = H1 - H0;

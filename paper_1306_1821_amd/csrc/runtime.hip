@@ -832,6 +832,7 @@ hmc_status gibbs_sweep(hmc_ctx* c, uint64_t sweep_index, hmc_sweep_stats* out) {
       out[i].accepted = k.hp[kAcc] != 0.0;
       out[i].rj_dH = k.cfg.rj_move ? k.hp[kRjDH] : 0.0;
       out[i].rj_accepted = k.cfg.rj_move ? k.hp[kRjAcc] != 0.0 : 0;
+      out[i].rj_wall_hits = k.cfg.rj_move ? (int32_t)k.hp[kRjHits] : 0;
       out[i].pk = c->stat_pk.data() + po;
       out[i].bias = c->stat_bias.data() + bo;
       out[i].nbar = c->stat_nbar.data() + bo;
@@ -845,7 +846,7 @@ hmc_status gibbs_sweep(hmc_ctx* c, uint64_t sweep_index, hmc_sweep_stats* out) {
 size_t hmc_sweep_record_doubles(const hmc_ctx* c) {
   if (!c) return 0;
   size_t n = 0;
-  for (auto& k : c->ch) n += 5 + k.dev.nb + 2 * k.dev.nsub;
+  for (auto& k : c->ch) n += kRecHead + k.dev.nb + 2 * k.dev.nsub;
   return n;
 }
 

@@ -189,10 +189,12 @@ def test_async_calls_equal_synchronous_ones():
             nb, c = len(st["pk"]), len(st["bias"])
             assert r[0] == st["dH"] and bool(r[1]) == st["accepted"]
             assert r[2] == st["rj_dH"] and bool(r[3]) == st["rj_accepted"] and r[4] == 0
-            assert np.array_equal(r[5:5 + nb], st["pk"])
-            assert np.array_equal(r[5 + nb:5 + nb + c], st["bias"])
-            assert np.array_equal(r[5 + nb + c:5 + nb + 2 * c], st["nbar"])
-            off += 5 + nb + 2 * c
+            assert r[5] == st["rj_wall_hits"]
+            h = 6
+            assert np.array_equal(r[h:h + nb], st["pk"])
+            assert np.array_equal(r[h + nb:h + nb + c], st["bias"])
+            assert np.array_equal(r[h + nb + c:h + nb + 2 * c], st["nbar"])
+            off += h + nb + 2 * c
     for i in range(2):
         assert np.array_equal(a.state(i)["delta_k"], b.state(i)["delta_k"])
     a.close()
