@@ -98,7 +98,8 @@ def joint_move(dk, lam, post, n_modes, cfg, s, rho0=None):
     dH = H1 - H0
     u = philox.uniform(seed, chain, philox.STREAM_RJ_ACCEPT, s)
     acc = bool(np.log(u) < -dH)
-    return dict(dH=dH, accepted=acc, theta=theta, rho=rho, H0=H0, H1=H1, mass=mass,
+    return dict(dH=dH, accepted=acc, log_u=float(np.log(u)), theta=theta, rho=rho, H0=H0, H1=H1,
+                mass=mass,
                 wall_hits=int(hits.sum()), dk_prop=dk1,
                 dk=dk1 if acc else dk, lam=np.exp(theta) if acc else np.asarray(lam, float),
                 grad=gk1 if acc else None)

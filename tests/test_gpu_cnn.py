@@ -28,7 +28,7 @@ def case(n, seed):
     return params, x, target
 
 
-@pytest.mark.parametrize("n", [8, 16, 32])
+@pytest.mark.parametrize("n", [8, 16, 32, 64, 128])
 def test_forward_matches_oracle(n):
     params, x, target = case(n, n)
     net = CNN(params)
@@ -40,7 +40,7 @@ def test_forward_matches_oracle(n):
     net.close()
 
 
-@pytest.mark.parametrize("n", [8, 16])
+@pytest.mark.parametrize("n", [8, 16, 32, 64])     # 64^3: more bricks than weight-gradient blocks
 def test_gradients_match_oracle(n):
     params, x, target = case(n, 100 + n)
     net = CNN(params)
