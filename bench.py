@@ -565,15 +565,23 @@ def main():
                              "ypass": ms_all[1] / max(1, launches_all[1]),
                              "zpass": ms_all[2] / max(1, launches_all[2])},
     }
-    # the whole step (x + 2 y + z passes, HIP events) against two byte counts: the
-    # fused four-pass design's 56 N^3 bytes and the 40 N^3 bytes of a step whose two
-    # FFTs take the minimum two passes each over a grid larger than on-chip memory
-    step_ms = (out["pass_ms_per_step"]["kspace"] + 2 * out["pass_ms_per_step"]["ypass"]
-               + out["pass_ms_per_step"]["zpass"])
+    # the whole step against two byte counts: the design's own and the 40 N^3 bytes of
+    # a step whose two FFTs take the minimum two passes each over a grid larger than
+    # on-chip memory.  With the fused y-z plane pass a step is the k-space pass plus
+    # one plane pass (40 N^3 bytes; the y passes left run only in the momentum draw);
+    # otherwise it is x + 2 y + z passes (56 N^3 bytes).
+    plane = launches_all[1] < launches_all[2]
+    pm = out["pass_ms_per_step"]
+    if plane:
+        step_ms, design = pm["kspace"] + pm["zpass"], 40
+        out["pass_ms_per_step"]["plane"] = pm.pop("zpass")
+    else:
+        step_ms, design = pm["kspace"] + 2 * pm["ypass"] + pm["zpass"], 56
     nv = n ** 3
     out["step_roofline"] = {
-        "ms": step_ms, "bytes_fused_design": 56 * nv, "bytes_lower_bound": 40 * nv,
-        "frac_fused_design": 56 * nv / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "ms": step_ms, "passes": "x + yz plane" if plane else "x + 2 y + z",
+        "bytes_design": design * nv, "bytes_lower_bound": 40 * nv,
+        "frac_design": design * nv / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "frac_lower_bound": 40 * nv / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
     s.close()
     del s

@@ -230,6 +230,16 @@ hmc_status hmc_set_launch(hmc_ctx* ctx, int32_t pass_class, int32_t grid);
  * HMC_EINVAL on a bad class or plan. */
 hmc_status hmc_set_plan(hmc_ctx* ctx, int32_t pass_class, int32_t plan);
 
+/* Fused y-z plane pass (enable = 1, the default) or separate passes (0) for
+ * the gradient evaluations of contexts whose chains all have one grid size with
+ * a plane pass (256^3).  The fused pass runs, per real-space x plane, the
+ * inverse y transforms, the C2R z transforms, the data force of eq.
+ * Wiener_Posterior_force, the R2C z transforms and the forward y transforms
+ * with the plane on chip, so a leapfrog step moves 40 N^3 instead of 56 N^3
+ * bytes.  Results agree with the separate passes to float32 rounding, not
+ * bitwise.  Captured graphs are dropped.  HMC_EINVAL unless enable is 0 or 1. */
+hmc_status hmc_set_plane_pass(hmc_ctx* ctx, int32_t enable);
+
 /* The launch configuration in force: grid[3] in the form hmc_set_launch takes,
  * plan[3] as hmc_set_plan (host arrays, either may be NULL). */
 hmc_status hmc_get_launch(hmc_ctx* ctx, int32_t* grid, int32_t* plan);

@@ -49,8 +49,9 @@ EXPORTS = ["hmc_workspace_bytes", "hmc_init", "hmc_init_batch", "leapfrog_trajec
            "hmc_autotune", "hmc_set_coefficients", "hmc_get_params", "hmc_shell_index",
            "hmc_set_mass", "hmc_set_mass_diagonal", "hmc_field_moments",
            "hmc_timing", "hmc_use_graph", "hmc_last_error", "hmc_destroy",
+           "hmc_set_plane_pass",
            "cnn_param_count", "cnn_create", "cnn_get_params", "cnn_forward", "cnn_gradient",
-           "cnn_features",
+           "cnn_features", "cnn_layer_state",
            "cnn_train_step", "cnn_last_error", "cnn_destroy"]
 
 _lib = None
@@ -89,6 +90,7 @@ def lib(path=LIB_PATH):
     L.hmc_set_launch.argtypes = [P, I32, I32]
     L.hmc_autotune.argtypes = [P, I32, ctypes.POINTER(I32)]
     L.hmc_set_plan.argtypes = [P, I32, I32]
+    L.hmc_set_plane_pass.argtypes = [P, I32]
     L.hmc_get_launch.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I32)]
     L.hmc_set_coefficients.argtypes = [P, I32, P, P]
     L.hmc_get_params.argtypes = [P, I32, D, D, D]
@@ -111,6 +113,7 @@ def lib(path=LIB_PATH):
     L.cnn_gradient.argtypes = [P, I32, P, P, F, D]
     L.cnn_features.argtypes = [P, I32, P, ctypes.c_float, P, P, P]
     L.cnn_train_step.argtypes = [P, I32, P, P, ctypes.c_float, D]
+    L.cnn_layer_state.argtypes = [P, I32, P, P, P]
     L.cnn_last_error.argtypes = [P]
     L.cnn_last_error.restype = ctypes.c_char_p
     L.cnn_destroy.argtypes = [P]
@@ -352,6 +355,10 @@ class Sampler:
         of 64^3 .. 256^3 grids; plans other than 0 change rounding."""
         self._check(self.L.hmc_set_plan(self.ctx, int(pass_class), int(plan)))
 
+    def set_plane_pass(self, enable=True):
+        """Fused y-z plane pass (256^3 single-size contexts) or separate y, z, y passes."""
+        self._check(self.L.hmc_set_plane_pass(self.ctx, int(bool(enable))))
+
     def launch_config(self):
         """(grids, plans) in force, three of each (pass classes x, y, z)."""
         g, p = (ctypes.c_int32 * 3)(), (ctypes.c_int32 * 3)()
@@ -483,6 +490,19 @@ class CNN:
                                         g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
                                         ctypes.byref(loss)))
         return g, loss.value
+
+    def layer_state(self, layer, n):
+        """Host float64 copies (z, a, dz) of layer `layer` from the last gradient
+        evaluation on an N^3 grid, each [N^3, C_out] (a is None for layer 3)."""
+        cout = CNN_LAYERS[layer][1]
+        mk = lambda: self.torch.empty((n ** 3, cout), dtype=self.torch.float32, device=self.device)
+        z, dz = mk(), mk()
+        a = mk() if layer < 3 else None
+        self._check(self.L.cnn_layer_state(self.ctx, int(layer), ctypes.c_void_p(z.data_ptr()),
+                                           ctypes.c_void_p(a.data_ptr() if a is not None else None),
+                                           ctypes.c_void_p(dz.data_ptr())))
+        f = lambda t: None if t is None else t.cpu().numpy().astype(np.float64)
+        return f(z), f(a), f(dz)
 
     def train_step(self, inputs, target, lr):
         x, t = self._dev(inputs), self._dev(target)

@@ -209,7 +209,8 @@ __device__ __forceinline__ int lds_at(int i, int es) {
   }
 }
 
-template <int N, int T, int R, int NS, int DIR, bool LAST, bool WAVE = false, int PAD = 0>
+template <int N, int T, int R, int NS, int DIR, bool LAST, bool WAVE = false, int PAD = 0,
+          bool DTW = false>
 __device__ __forceinline__ void stage(float2* v, float2* lds, int es, int t, bool active,
                                       const float2* __restrict__ tw) {
   constexpr int E = N / T;
@@ -225,7 +226,7 @@ __device__ __forceinline__ void stage(float2* v, float2* lds, int es, int t, boo
     if constexpr (NS > 1) {
       constexpr int step = N / (NS * R);
 #if HMC_TW_POW2
-    if constexpr (N >= 128) {
+    if constexpr (N >= 128 && !DTW) {
       // large N: twiddles W^(r k) for every r from the table entries at powers of
       // two of r (at most three complex products each, fewer live registers)
       float2 wp[5];
@@ -276,12 +277,12 @@ __device__ __forceinline__ void stage(float2* v, float2* lds, int es, int t, boo
   }
 }
 
-template <int N, int T, int DIR, bool WAVE, int PAD, int NS, int R, int... Rest>
+template <int N, int T, int DIR, bool WAVE, int PAD, bool DTW, int NS, int R, int... Rest>
 __device__ __forceinline__ void stages(float2* v, float2* lds, int es, int t, bool active,
                                        const float2* __restrict__ tw) {
   constexpr bool last = sizeof...(Rest) == 0;
-  stage<N, T, R, NS, DIR, last, WAVE, PAD>(v, lds, es, t, active, tw);
-  if constexpr (!last) stages<N, T, DIR, WAVE, PAD, NS * R, Rest...>(v, lds, es, t, active, tw);
+  stage<N, T, R, NS, DIR, last, WAVE, PAD, DTW>(v, lds, es, t, active, tw);
+  if constexpr (!last) stages<N, T, DIR, WAVE, PAD, DTW, NS * R, Rest...>(v, lds, es, t, active, tw);
 }
 
 // Full length-N transform of the pencil held in v (cyclic in and out).
@@ -291,14 +292,27 @@ __device__ __forceinline__ void stages(float2* v, float2* lds, int es, int t, bo
 template <int N, int T, int DIR, int... Rs>
 __device__ __forceinline__ void fft(float2* v, float2* lds, int es, int t, bool active,
                                     const float2* __restrict__ tw, Radices<Rs...>) {
-  stages<N, T, DIR, false, 0, 1, Rs...>(v, lds, es, t, active, tw);
+  stages<N, T, DIR, false, 0, false, 1, Rs...>(v, lds, es, t, active, tw);
 }
 // the same with wavefront-scope ordering (every pencil inside one wavefront) and
 // an optional padded LDS layout (lds_at)
 template <int N, int T, int DIR, int PAD = 0, int... Rs>
 __device__ __forceinline__ void fft_wave(float2* v, float2* lds, int es, int t, bool active,
                                          const float2* __restrict__ tw, Radices<Rs...>) {
-  stages<N, T, DIR, true, PAD, 1, Rs...>(v, lds, es, t, active, tw);
+  stages<N, T, DIR, true, PAD, false, 1, Rs...>(v, lds, es, t, active, tw);
+}
+// variants that read every twiddle W^(r k) directly from the table instead of
+// forming it from the power-of-two entries: for tables staged in LDS, where a read
+// costs less than the complex products it replaces
+template <int N, int T, int DIR, int... Rs>
+__device__ __forceinline__ void fft_dtw(float2* v, float2* lds, int es, int t, bool active,
+                                        const float2* __restrict__ tw, Radices<Rs...>) {
+  stages<N, T, DIR, false, 0, true, 1, Rs...>(v, lds, es, t, active, tw);
+}
+template <int N, int T, int DIR, int PAD = 0, int... Rs>
+__device__ __forceinline__ void fft_wave_dtw(float2* v, float2* lds, int es, int t, bool active,
+                                             const float2* __restrict__ tw, Radices<Rs...>) {
+  stages<N, T, DIR, true, PAD, true, 1, Rs...>(v, lds, es, t, active, tw);
 }
 
 }  // namespace hmcfft

@@ -13,6 +13,8 @@
 // alpha_i = sum_l b_l^2 Nbar_l R^l_i and beta_i = sum_l b_l (N^l_i - Nbar_l R^l_i)
 // are precomputed once per sweep.  The unitary normalisation N^(-3/2) is
 // applied in the x-pass (both directions).
+#include <type_traits>
+
 #include "kernels.hpp"
 #include "fft.hpp"
 #include "rng.hpp"
@@ -277,6 +279,14 @@ __device__ __forceinline__ void zfft(float2* v, float2* lds, int t, bool active,
 #else
   fft<N, T, DIR>(v, lds, 1, t, active, tw, RL{});
 #endif
+}
+
+// the same with every twiddle read directly from an LDS-staged table
+template <int N, int T, int DIR, class RL>
+__device__ __forceinline__ void zfft_dtw(float2* v, float2* lds, int t, bool active,
+                                         const float2* __restrict__ tw) {
+  static_assert(64 % T == 0 && HMC_ZWAVE, "a z-pass row must not straddle wavefronts");
+  fft_wave_dtw<N, T, DIR, HMC_ZLPAD ? 4 : 0>(v, lds, 1, t, active, tw, RL{});
 }
 
 // Real-transform partner of a row held by T consecutive lanes (T divides 16, rows
@@ -1035,6 +1045,250 @@ __global__ void __launch_bounds__(kThreads) k_zpass_n(const ChainDev* __restrict
   }
 }
 
+
+// ------------------------------------------------------------------ y-z plane pass
+// One workgroup per real-space x plane of T (T holds the x pass's inverse x
+// transform): inverse y transforms of the plane's kz columns, C2R along z, the
+// data force g = alpha delta - beta, R2C along z and forward y transforms, with
+// the plane on chip throughout.  It replaces the y, z, y pass sequence of a
+// gradient evaluation, so the plane makes one round trip through HBM instead of
+// three (T, alpha, beta read and T written once: 40 N^3 bytes per leapfrog step
+// with the k-space pass instead of 56 N^3).
+//
+// The plane (N x (N/2+1) complex, 264 KB at 256^3) does not fit in LDS; it lives
+// in the registers of a 512-thread workgroup (64 values per thread) and moves
+// through LDS in chunks of rows for the column <-> row transposes.  The two
+// self-conjugate columns kz = 0 and kz = M = N/2 travel as one complex column
+// Z = C_0 + i C_M: both are Hermitian in ky (the field is real), so the inverse y
+// transform of Z is y_0 + i y_M with y_0, y_M real, which are the real X_0, X_M
+// every z row needs (the imaginary parts a C2R drops).  On the way back the real
+// X_0, X_M of each row are packed the same way and separated after the forward y
+// transform: A_k = (Z_k + conj Z_{-k}) / 2, B_k = -i (Z_k - conj Z_{-k}) / 2.
+template <int N> struct PC;
+template <> struct PC<256> {
+  static constexpr int P = 512;          // threads per workgroup
+  static constexpr int TY = 16;          // threads per y pencil (cyclic, 16 values each)
+  using RLY = Radices<16, 16>;
+  static constexpr int TZ = 16;          // threads per z row (cyclic, 8 values each)
+  using RLZ = Radices<8, 4, 4>;          // the half-length (128-point) complex transform
+  static constexpr int GL = 1;           // pencil groups that wait in LDS instead of registers
+};
+template <int N> constexpr bool has_plane() { return N == 256; }
+// LDS layout in float2: [0, A) the y-transform exchange and the z-row chunk buffer
+// (used in turn), [A, A + N LS) the columns kept in LDS (row-major, stride LS),
+// then N values for separating column 0
+template <int N> struct PL {
+  using C = PC<N>;
+  static constexpr int M = N / 2, PY = C::P / C::TY, RZ = C::P / C::TZ;
+  static constexpr int LY = N * (PY + 1), LZ = RZ * zrs<N>();
+  static constexpr int A = LY > LZ ? LY : LZ;
+  static constexpr int LS = C::GL * PY + 1;
+  static constexpr int TOTAL = A + N * LS + N;
+};
+
+// compile-time loop: f(std::integral_constant<int, I>) for I = B .. E-1, so that
+// register arrays indexed by I stay in registers however large the body is
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
+template <int N>
+__device__ __forceinline__ void yzpass(const ChainDev& d, int x, const ZArgs a, float2* lds,
+                                       const float2* stw, double* red) {
+  using C = PC<N>;
+  using L = PL<N>;
+  constexpr int M = N / 2, H = M + 1;
+  constexpr int P = C::P, TY = C::TY, EY = N / TY, PY = P / TY, G = M / PY;
+  constexpr int GL = C::GL, GR = G - GL, CR = GR * PY;  // register groups, their columns
+  constexpr int TZ = C::TZ, EZ = M / TZ, RZ = P / TZ, NCH = N / RZ, EC = RZ / TY;
+  constexpr int ESY = PY + 1, RSZ = zrs<N>(), LS = L::LS;
+  static_assert(M % PY == 0 && N % RZ == 0 && RZ % TY == 0 && EY % EC == 0, "plane tiling");
+  static_assert(64 % TZ == 0 && TZ <= 16, "a z row sits in one DPP row group of a wavefront");
+  static_assert(CR % TZ == 0 && GR >= 1, "register / LDS column split on a row-thread boundary");
+  const int tid = threadIdx.x;
+  const int b = tid % PY, t = tid / PY;   // column phase: pencil b of each group, its thread t
+  const int r = tid / TZ, tz = tid % TZ;  // row phase: row r of the chunk, its thread tz
+  // twiddles staged in LDS: W_M^i (i < M), W_N^k (k < M), then W_N^i (i < N) for the
+  // y transforms (read from LDS, they are not kept in registers across the phases)
+  const float2* twM = stw;
+  const float2* twN = stw + M;
+  const float2* twy = stw + N;
+  float2* const Ls = lds + L::A;          // columns CR .. M-1, [y][c - CR]
+  // addresses: a uniform (scalar) base per element plus one per-thread offset, so
+  // that the loads and stores of the plane share a single offset register
+  float2* const Pl = d.T + (size_t)x * (N * H);
+  const uint32_t toff = (uint32_t)(t * H + b);
+  auto at = [&](int g, int e) {
+    // the row base is pinned in scalar registers: left to itself the compiler folds
+    // the constant into a 64-bit vector address per element and runs out of registers
+    float2* p = Pl + TY * e * H;
+    asm volatile("" : "+s"(p));
+    return p + g * PY;
+  };
+
+  // the plane: packed column c = g PY + b, rows y = t + TY e (every load first);
+  // groups below GR stay in registers, the others wait in LDS between the phases
+  // column 0 of group 0 carries kz = 0 and kz = M: Z = C_0 + i C_M.  The kz = M
+  // values are loaded first, so that waiting for them does not wait for the rest
+  // of the plane (loads complete in order)
+  float2 cm[EY];
+  if (b == 0) {
+#pragma unroll
+    for (int e = 0; e < EY; ++e) cm[e] = gldi(at(0, e) + M, toff);
+  }
+  float2 v[GR][EY], u[GL > 0 ? GL : 1][EY];
+#pragma unroll
+  for (int g = 0; g < G; ++g)
+#pragma unroll
+    for (int e = 0; e < EY; ++e) {
+      const float2 val = gldi(at(g, e), toff);
+      if (g < GR) v[g < GR ? g : 0][e] = val; else u[g < GR ? 0 : g - GR][e] = val;
+    }
+  if (b == 0) {
+#pragma unroll
+    for (int e = 0; e < EY; ++e) v[0][e] = make_float2(v[0][e].x - cm[e].y, v[0][e].y + cm[e].x);
+  }
+  static_for<0, G>([&](auto gc) {
+    constexpr int g = decltype(gc)::value;
+    if constexpr (g < GR) {
+      fft_dtw<N, TY, -1>(v[g], lds + b, ESY, t, true, twy, typename C::RLY{});
+    } else {
+      fft_dtw<N, TY, -1>(u[g - GR], lds + b, ESY, t, true, twy, typename C::RLY{});
+#pragma unroll
+      for (int e = 0; e < EY; ++e) Ls[(t + TY * e) * LS + (g - GR) * PY + b] = u[g - GR][e];
+    }
+  });
+
+  const float2* ap = reinterpret_cast<const float2*>(d.alpha);
+  const float2* bp = reinterpret_cast<const float2*>(d.beta);
+  float* drout = (a.flags & ZF_WRITE_DRN) ? d.drn : (a.flags & ZF_WRITE_DR) ? d.dr : nullptr;
+  float2* const Lr = lds + r * RSZ;  // this thread's row of the chunk buffer
+  double dat = 0.0;
+  static_for<0, NCH>([&](auto qc) {
+    constexpr int q = decltype(qc)::value;
+    const size_t rq = ((size_t)x * N + q * RZ) * M;   // the chunk's first voxel pair (uniform)
+    const uint32_t ro = (uint32_t)(r * M + tz);        // this thread's pair in the chunk
+    float2* const Lsr = Ls + (q * RZ + r) * LS - CR;   // this row's columns CR.. in LDS
+    const float2* ab = ap + rq;
+    const float2* bb = bp + rq;
+    asm volatile("" : "+s"(ab), "+s"(bb));  // scalar bases, one offset register (see at())
+    float2 al[EZ], be[EZ];
+#pragma unroll
+    for (int e = 0; e < EZ; ++e) {
+      al[e] = ld_si(ab + TZ * e, ro);
+      be[e] = ld_si(bb + TZ * e, ro);
+    }
+    __syncthreads();  // the buffer's previous readers are done
+#pragma unroll
+    for (int g = 0; g < GR; ++g)
+#pragma unroll
+      for (int j = 0; j < EC; ++j) lds[(t + TY * j) * RSZ + g * PY + b] = v[g][EC * q + j];
+    __syncthreads();
+    float2 xr[EZ + 1], w[EZ];
+#pragma unroll
+    for (int e = 0; e < EZ; ++e) {
+      const int k = tz + TZ * e;
+      xr[e] = TZ * e < CR ? Lr[k] : Lsr[k];
+    }
+    xr[EZ] = make_float2(xr[0].y, 0.f);  // lane 0: X_M from the packed column (X_0 = Re xr[0])
+    c2r_pre<N, TZ, EZ>(xr, w, Lr, tz, twN);
+    zfft_dtw<M, TZ, -1, typename C::RLZ>(w, Lr, tz, true, twM);
+#pragma unroll
+    for (int e = 0; e < EZ; ++e) {
+      const float2 xv = w[e];
+      if (drout) gsti(reinterpret_cast<float2*>(drout) + rq + TZ * e, ro, xv);  // trajectory ends
+      if (a.flags & ZF_DATA)
+        dat += (0.5 * al[e].x * xv.x - be[e].x) * (double)xv.x +
+               (0.5 * al[e].y * xv.y - be[e].y) * (double)xv.y;
+      w[e] = make_float2(al[e].x * xv.x - be[e].x, al[e].y * xv.y - be[e].y);
+    }
+    zfft_dtw<M, TZ, +1, typename C::RLZ>(w, Lr, tz, true, twM);
+    float x0 = 0.f;
+    r2c_post<N, TZ, EZ>(w, Lr, tz, true, twN, [&](int k, float2 X) {
+      if (k == 0)
+        x0 = X.x;
+      else if (k == M)
+        Lr[0] = make_float2(x0, X.x);  // packed column 0: X_0 + i X_M
+      else if (k < CR)
+        Lr[k] = X;
+      else
+        Lsr[k] = X;
+    });
+    __syncthreads();
+#pragma unroll
+    for (int g = 0; g < GR; ++g)
+#pragma unroll
+      for (int j = 0; j < EC; ++j) v[g][EC * q + j] = lds[(t + TY * j) * RSZ + g * PY + b];
+  });
+  __syncthreads();
+  // forward y transforms, each group stored as soon as it is done (the stores drain
+  // while the next group transforms); column 0 of group 0 is separated first
+  float2* const Lu = lds + (L::TOTAL - N);
+  static_for<0, G>([&](auto gc) {
+    constexpr int g = decltype(gc)::value;
+    if constexpr (g < GR) {
+      fft_dtw<N, TY, +1>(v[g], lds + b, ESY, t, true, twy, typename C::RLY{});
+      if constexpr (g == 0) {
+        // A_k = (Z_k + conj Z_-k) / 2 -> kz = 0, B_k = -i (Z_k - conj Z_-k) / 2 -> kz = M
+        if (b == 0) {
+#pragma unroll
+          for (int e = 0; e < EY; ++e) Lu[t + TY * e] = v[0][e];
+        }
+        __syncthreads();
+        if (b == 0) {
+          float2 cb[EY];
+#pragma unroll
+          for (int e = 0; e < EY; ++e) {
+            const int k = t + TY * e;
+            const float2 z = v[0][e], zc = cconj(Lu[(N - k) & (N - 1)]);
+            const float2 df = csub(z, zc);
+            v[0][e] = make_float2(0.5f * (z.x + zc.x), 0.5f * (z.y + zc.y));
+            cb[e] = make_float2(0.5f * df.y, -0.5f * df.x);
+          }
+#pragma unroll
+          for (int e = 0; e < EY; ++e) gsti(at(0, e) + M, toff, cb[e]);
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < EY; ++e) gsti(at(g, e), toff, v[g][e]);
+    } else {
+#pragma unroll
+      for (int e = 0; e < EY; ++e) u[g - GR][e] = Ls[(t + TY * e) * LS + (g - GR) * PY + b];
+      fft_dtw<N, TY, +1>(u[g - GR], lds + b, ESY, t, true, twy, typename C::RLY{});
+#pragma unroll
+      for (int e = 0; e < EY; ++e) gsti(at(g, e), toff, u[g - GR][e]);
+    }
+  });
+  if (a.flags & ZF_DATA) {
+    // the plane's data energy into the first of its z-pass tiles, zeros into the others
+    constexpr int tpp = N / ZC<N>::B;
+    const double sd = block_sum_w<P / 64>(dat, red);
+    if (tid < tpp) d.part[kPartDat * d.maxtiles + x * tpp + tid] = tid == 0 ? sd : 0.0;
+  }
+}
+
+// single-size launch: N consecutive workgroups per chain, one per x plane
+template <int N>
+__global__ void __launch_bounds__(PC<N>::P) k_yzpass_n(const ChainDev* __restrict__ ch, ZArgs a,
+                                                        const float2* __restrict__ tw) {
+  __shared__ float2 lds[PL<N>::TOTAL];
+  __shared__ float2 stw[2 * N];
+  __shared__ double red[PC<N>::P / 64];
+  for (int i = threadIdx.x; i < 2 * N; i += PC<N>::P)
+    stw[i] = i < N / 2 ? tw[tw_offset(N / 2) + i] : i < N ? tw[tw_offset(N) + i - N / 2] : tw[tw_offset(N) + i - N];
+  __syncthreads();
+  yzpass<N>(ch[blockIdx.x / N], (int)(blockIdx.x % N), a, lds, stw, red);
+}
+
+bool plane_pass_supported(int n) { return n == 256; }
+void launch_yzpass(const ChainDev* ch, int nch, ZArgs a, const float2* tw, hipStream_t s, int n) {
+  if (n == 256)
+    hipLaunchKernelGGL(k_yzpass_n<256>, dim3(nch * 256), dim3(PC<256>::P), 0, s, ch, a, tw);
+}
 
 // ------------------------------------------------------------------ learned mass
 // Inverse mass T T^T, T = P D^(1/2) F^-1 diag(m_k^-1/2) (P removes the mean):
@@ -1804,56 +2058,71 @@ __global__ void __launch_bounds__(kThreads) k_energy_k(const ChainDev* __restric
 //   SP_DOT:   sum w Re(conj(delta_hat) g_hat) of the stored state and gradient
 //             (the joint move's dU at its start).
 enum ShellSum : int { SP_POWER = 0, SP_DOT = 1 };
+constexpr int kShellWaves = kWideThreads / 64;
+
+// One tile of kElemPerTile modes of a field dk (and gk for SP_DOT) into sig[m * sstride]
+// and, when cnt_out is set, the mode counts into cnt_out[m]; bins and cnt are the
+// block's LDS bins (one copy per wave), summed in a fixed order (reproducible).
+template <int WHAT>
+__device__ __forceinline__ void shell_sum_tile(const float2* __restrict__ dk,
+                                               const float2* __restrict__ gk, int n, int nb,
+                                               long long nh, int lt, double* sig, size_t sstride,
+                                               double* cnt_out, double* bins, double* cnt) {
+  const bool with_counts = cnt_out != nullptr;
+  for (int i = threadIdx.x; i < kShellWaves * kMaxBins; i += kWideThreads) {
+    bins[i] = 0.0;
+    cnt[i] = 0.0;
+  }
+  __syncthreads();
+  const int wv = (threadIdx.x >> 6) * kMaxBins;
+  const uint32_t qmax = 3u * (uint32_t)(n / 2) * (uint32_t)(n / 2), nbu = (uint32_t)nb;
+  const float inv_qmax = 1.f / (float)qmax;
+  for (int j = threadIdx.x; j < kElemPerTile; j += kWideThreads) {
+    const long long i = (long long)lt * kElemPerTile + j;
+    if (i >= nh) break;
+    int fx, fy, kz;
+    kindex(i, n, &fx, &fy, &kz);
+    const int m = shell_fast((uint32_t)(fx * fx + fy * fy + kz * kz), qmax, inv_qmax, nbu);
+    if (m < 0) continue;
+    const double w = (kz == 0 || kz == n / 2) ? 1.0 : 2.0;
+    const float2 x = dk[i];
+    double val;
+    if constexpr (WHAT == SP_POWER) {
+      val = w * ((double)x.x * x.x + (double)x.y * x.y);
+    } else {
+      const float2 g = gk[i];
+      val = w * ((double)x.x * g.x + (double)x.y * g.y);
+    }
+    atomicAdd(&bins[wv + m], val);
+    if (WHAT == SP_POWER && with_counts) atomicAdd(&cnt[wv + m], w);
+  }
+  __syncthreads();
+  for (int m = threadIdx.x; m < nb; m += kWideThreads) {
+    double sb = 0.0, sc = 0.0;
+#pragma unroll
+    for (int c = 0; c < kShellWaves; ++c) {  // fixed order: reproducible
+      sb += bins[c * kMaxBins + m];
+      sc += cnt[c * kMaxBins + m];
+    }
+    sig[(size_t)m * sstride] = sb;
+    if (WHAT == SP_POWER && with_counts) cnt_out[m] = sc;
+  }
+  __syncthreads();
+}
+
 template <int WHAT>
 __global__ void __launch_bounds__(kWideThreads) k_shell_sum(const ChainDev* __restrict__ ch,
                                                             int nch, int total, int with_counts) {
   // one bin copy per wave; 1024-thread blocks keep 16 waves per tile in flight
   // (the per-mode work is a dependent chain of index arithmetic, not bandwidth)
-  constexpr int kWaves = kWideThreads / 64;
-  __shared__ double bins[kWaves * kMaxBins];
-  __shared__ double cnt[kWaves * kMaxBins];
+  __shared__ double bins[kShellWaves * kMaxBins];
+  __shared__ double cnt[kShellWaves * kMaxBins];
   for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
     const ChainDev& d = ch[find_chain(ch, nch, tile, kTileK)];
     const int lt = tile - d.tb[kTileK];
-    for (int i = threadIdx.x; i < kWaves * kMaxBins; i += kWideThreads) {
-      bins[i] = 0.0;
-      cnt[i] = 0.0;
-    }
-    __syncthreads();
-    const int wv = (threadIdx.x >> 6) * kMaxBins;
-    const uint32_t qmax = 3u * (uint32_t)(d.n / 2) * (uint32_t)(d.n / 2), nbu = (uint32_t)d.nb;
-    const float inv_qmax = 1.f / (float)qmax;
-    for (int j = threadIdx.x; j < kElemPerTile; j += kWideThreads) {
-      const long long i = (long long)lt * kElemPerTile + j;
-      if (i >= d.nh) break;
-      int fx, fy, kz;
-      kindex(i, d.n, &fx, &fy, &kz);
-      const int m = shell_fast((uint32_t)(fx * fx + fy * fy + kz * kz), qmax, inv_qmax, nbu);
-      if (m < 0) continue;
-      const double w = (kz == 0 || kz == d.n / 2) ? 1.0 : 2.0;
-      const float2 x = d.dk[i];
-      double val;
-      if constexpr (WHAT == SP_POWER) {
-        val = w * ((double)x.x * x.x + (double)x.y * x.y);
-      } else {
-        const float2 g = d.gk[i];
-        val = w * ((double)x.x * g.x + (double)x.y * g.y);
-      }
-      atomicAdd(&bins[wv + m], val);
-      if (WHAT == SP_POWER && with_counts) atomicAdd(&cnt[wv + m], w);
-    }
-    __syncthreads();
-    for (int m = threadIdx.x; m < d.nb; m += kWideThreads) {
-      double sb = 0.0, sc = 0.0;
-#pragma unroll
-      for (int c = 0; c < kWaves; ++c) {  // fixed order: reproducible
-        sb += bins[c * kMaxBins + m];
-        sc += cnt[c * kMaxBins + m];
-      }
-      d.shpart[(size_t)m * d.maxtiles + lt] = sb;
-      if (WHAT == SP_POWER && with_counts) d.mpart[(size_t)lt * d.nb + m] = sc;
-    }
-    __syncthreads();
+    shell_sum_tile<WHAT>(d.dk, d.gk, d.n, d.nb, d.nh, lt, d.shpart + lt, d.maxtiles,
+                         (WHAT == SP_POWER && with_counts) ? d.mpart + (size_t)lt * d.nb : nullptr,
+                         bins, cnt);
   }
 }
 
@@ -1949,6 +2218,11 @@ __global__ void __launch_bounds__(kThreads) k_reduce_slot(const ChainDev* __rest
 // Column sums of per-tile partials (src 0: shpart [shell][tile]; src 1: mpart
 // [tile][width]), one block per (column, chain), fixed order (strided per thread,
 // then the block tree).
+__device__ __forceinline__ double column_sum(const double* p, size_t step, int nt, double* red) {
+  double acc = 0.0;
+  for (int t = threadIdx.x; t < nt; t += kThreads) acc += p[(size_t)t * step];
+  return block_sum(acc, red);
+}
 // mode 0: P[dst + q] = sum (per-shell tables, width nb)
 // mode 1: P[dst + (q % 3) * kMaxSub + q / 3] = sum (moments, width 3 nsub)
 // mode 2: P[dst + q] = sum / 2 + (alpha_prior - 1) (joint-move dU, width nb)
@@ -1959,14 +2233,10 @@ __global__ void __launch_bounds__(kThreads) k_colsum(const ChainDev* __restrict_
   const int q = blockIdx.x;
   const int width = mode == 1 ? 3 * d.nsub : d.nb;
   if (q >= width) return;
-  double acc = 0.0;
-  if (src == 0) {  // shell partials, [shell][tile]: a block reads one contiguous row
-    const double* p = d.shpart + (size_t)q * d.maxtiles;
-    for (int t = threadIdx.x; t < d.nt[cls]; t += kThreads) acc += p[t];
-  } else {
-    for (int t = threadIdx.x; t < d.nt[cls]; t += kThreads) acc += d.mpart[(size_t)t * width + q];
-  }
-  const double s = block_sum(acc, red);
+  // shell partials are [shell][tile] (a block reads one contiguous row), the
+  // others [tile][width]
+  const double s = src == 0 ? column_sum(d.shpart + (size_t)q * d.maxtiles, 1, d.nt[cls], red)
+                            : column_sum(d.mpart + q, (size_t)width, d.nt[cls], red);
   if (threadIdx.x == 0) {
     if (mode == 0) d.P[dst + q] = s;
     else if (mode == 1) d.P[dst + (q % 3) * kMaxSub + q / 3] = s;

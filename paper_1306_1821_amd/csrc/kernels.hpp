@@ -4,6 +4,7 @@
 
 namespace hmc {
 
+
 // x-pass modes (k-space side of a leapfrog step; see kernels.hip)
 enum XMode : int { X_INV = 0, X_FWD = 1, X_START = 2, X_STEP = 3, X_END = 4 };
 // x-pass flags
@@ -62,6 +63,10 @@ void launch_zpass_learned(int mode, const ChainDev* ch, int nch, int total, int 
                           const float2* tw, int grid_cap, hipStream_t s, int uniform_n);
 void launch_mass_prep(int phase, const ChainDev* ch, int total_r, const float* logvar,
                       hipStream_t s);
+// y-z plane pass (inverse y, C2R z, data force, R2C z, forward y in one kernel)
+// for single-size launches of the grid sizes it supports
+bool plane_pass_supported(int n);
+void launch_yzpass(const ChainDev* ch, int nch, ZArgs a, const float2* tw, hipStream_t s, int n);
 void launch_zpass(int mode, const ChainDev* ch, int nch, int total, int lds, ZArgs a,
                   const float2* tw, int grid_cap, hipStream_t s, int uniform_n, int plan = 0);
 void launch_export(const ChainDev* ch, int nch, int sweep, double* rec, int32_t* acc,

@@ -118,6 +118,7 @@ struct hmc_ctx {
   std::vector<Group> groups;
   bool grouped[3] = {false, false, false};  // per pass class (x, y, z)
   int plan[3] = {0, 0, 0};  // radix plan per pass class for single-size launches
+  bool plane_pass = true;   // fused y-z plane pass where the grid size has one
   bool learned = false;      // every chain runs the learned mass
   bool mass_mixed = false;   // some chains only have a learned mass: no trajectories
   // pass timing (hmc_timing)
@@ -249,12 +250,24 @@ struct Seq {
     });
     tm.done(s);
   }
-  // g_hat, delta and the data energy of the current delta_hat
-  void gradient(int zflags, int xflags) {
-    x(X_INV, 0.f, 0.f, xflags & XF_SCALE);
+  // inverse y transforms, the real-space data force (C2R z, alpha delta - beta,
+  // R2C z) and forward y transforms: one fused plane pass for single-size
+  // contexts of a grid size that has one, else three passes
+  void yz(int zflags) {
+    if (c->plane_pass && un != 0 && plane_pass_supported(un)) {
+      Timed tm(c, 2, s);
+      launch_yzpass(d, nch, ZArgs{zflags, 0, nullptr}, c->tw, s, un);
+      tm.done(s);
+      return;
+    }
     y(-1);
     z(Z_GRAD, zflags);
     y(+1);
+  }
+  // g_hat, delta and the data energy of the current delta_hat
+  void gradient(int zflags, int xflags) {
+    x(X_INV, 0.f, 0.f, xflags & XF_SCALE);
+    yz(zflags);
     x(X_FWD, 0.f, 0.f, xflags);
   }
 };
@@ -674,14 +687,10 @@ static hmc_status run_trajectory(hmc_ctx* c) {
   launch_reduce_slot(c->d_all, nch, kPartKin, kK0, kTileXY, c->stream);
   launch_reduce_slot(c->d_all, nch, kPartPri, kPi0, kTileXY, c->stream);
   for (int s = 1; s < c->cur_steps; ++s) {
-    q.y(-1);
-    q.z(Z_GRAD, 0);
-    q.y(+1);
+    q.yz(0);
     q.x(X_STEP, 1.f, 1.f, 0);
   }
-  q.y(-1);
-  q.z(Z_GRAD, ZF_WRITE_DRN | ZF_DATA);
-  q.y(+1);
+  q.yz(ZF_WRITE_DRN | ZF_DATA);
   q.x(X_END, 0.5f, 0.f, 0);
   launch_reduce_slot(c->d_all, nch, kPartKin, kK1, kTileXY, c->stream);
   launch_reduce_slot(c->d_all, nch, kPartPri, kPi1, kTileXY, c->stream);
@@ -1016,6 +1025,13 @@ hmc_status hmc_set_plan(hmc_ctx* c, int32_t cls, int32_t plan) {
   if (!c || cls < 0 || cls > 2 || plan < 0 || plan >= kPlanCount)
     return fail(c, HMC_EINVAL, "bad argument");
   c->plan[cls] = plan;
+  drop_graphs(c);
+  return HMC_OK;
+}
+
+hmc_status hmc_set_plane_pass(hmc_ctx* c, int32_t enable) {
+  if (!c || (enable != 0 && enable != 1)) return fail(c, HMC_EINVAL, "bad argument");
+  c->plane_pass = enable != 0;
   drop_graphs(c);
   return HMC_OK;
 }

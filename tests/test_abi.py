@@ -92,3 +92,4 @@ def test_null_arguments(L):
 
 def test_cnn_parameter_count(L):
     assert L.cnn_param_count() == sum(27 * ci * co + co for ci, co in binding.CNN_LAYERS) == 16034
+

@@ -45,42 +45,41 @@ def test_graph_replays_equal_direct_launches():
         assert np.array_equal(x, y)
 
 
+@pytest.mark.timeout(300)
 def test_batched_chains_converge_together():
-    """Same-size chains in one batch sample the same P(k) posterior (split R-hat)."""
-    groups = [("small16", 4), ("cfg1", 2)]
-    specs, owner = [], []
-    cid = 0
-    for name, k in groups:
+    """Same-size chains in one batch sample the same P(k) posterior: rank-normalised
+    split R-hat below 1.01 on every data-informed shell, four chains per size.
+
+    The slowest shell is the first 32^3 shell (26 modes): with eps = 0.12 and 16
+    steps its bulk ESS grows by about 90 per 4000 sweeps over four chains (measured),
+    so 48000 sweeps put R-hat near 1.006; the 16^3 chains pass 1.01 by about 8000."""
+    groups = [("small16", 4, 0.08, 10, 16000), ("cfg1", 4, 0.12, 16, 48000)]
+    burn = 4000
+    for name, k, eps, nst, nsweep in groups:
         m = mock(name)
-        for _ in range(k):
-            specs.append(chain_spec(m, eps=0.08, nsteps=10, seed=41, chain_id=cid, rj=True))
-            owner.append(name)
-            cid += 1
-    s = Sampler(specs)
-    for i, name in enumerate(owner):
-        s.set_state(i, start_state(mock(name))[0])
-    s.use_graph(True)
-    nsweep, burn = 2000, 400
-    traces = [[] for _ in specs]
-    acc = []
-    for sw in range(nsweep):
-        out = s.sweep(sw)
-        acc.append([o["accepted"] for o in out])
-        for i, o in enumerate(out):
-            traces[i].append(np.log(o["pk"]))
-    s.close()
-    assert np.mean(acc) > 0.5
-    for name, _ in groups:
-        idx = [i for i, o in enumerate(owner) if o == name]
-        t = np.array([traces[i][burn:] for i in idx])          # chains x samples x shells
+        specs = [chain_spec(m, eps=eps, nsteps=nst, seed=41, chain_id=c, rj=True) for c in range(k)]
+        s = Sampler(specs)
+        for i in range(k):
+            s.set_state(i, start_state(m)[0])
+        s.use_graph(True)
+        traces = [[] for _ in specs]
+        acc = []
+        for sw in range(nsweep):
+            out = s.sweep(sw)
+            acc.append([o["accepted"] for o in out])
+            for i, o in enumerate(out):
+                traces[i].append(np.log(o["pk"]))
+        s.close()
+        assert np.mean(acc) > 0.5
+        t = np.array([tr[burn:] for tr in traces])          # chains x samples x shells
         nb = t.shape[2]
         # shells the data inform: centres below 0.7 of the Nyquist frequency
         # (k_corner = sqrt(3) k_Nyquist); the rest follow the flat Jeffreys tail
-        head = [m for m in range(nb) if (m + 0.5) / nb * np.sqrt(3.0) <= 0.7]
-        rh = [dg.split_rhat(t[:, :, m]) for m in head]
-        print(name, "max split R-hat over shells", max(rh), "min bulk ESS",
-              min(dg.ess_bulk(t[:, :, m]) for m in head))
-        assert max(rh) < 1.1, (name, rh)
+        head = [mm for mm in range(nb) if (mm + 0.5) / nb * np.sqrt(3.0) <= 0.7]
+        rh = [dg.split_rhat(t[:, :, mm]) for mm in head]
+        print(name, "split R-hat per shell", np.round(rh, 4), "min bulk ESS",
+              min(dg.ess_bulk(t[:, :, mm]) for mm in head), flush=True)
+        assert max(rh) < 1.01, (name, rh)
 
 
 @pytest.mark.parametrize("names", [("cfg1",), ("small16", "cfg1", "tiny8x2")])

@@ -185,6 +185,44 @@ def test_batched_mixed_sizes_match_oracle():
 
 
 @pytest.mark.timeout(300)
+def test_plane_pass_matches_separate_passes_and_oracle():
+    """At 256^3 the gradient evaluations run the fused y-z plane pass (inverse y,
+    C2R z, data force, R2C z, forward y with the plane on chip; the kz = 0 and
+    kz = N/2 columns travel as one complex column).  Against the separate y, z, y
+    passes and against the oracle: the gradient of set_state, the data energy,
+    the real field, and a trajectory's end point and dH."""
+    mk = mock("cfg3")
+    a32, b32 = coefficients32(mk)
+    d32, dk = start_state(mk)
+    post = oracle_posterior(mk, a32, b32, workers=16)
+    f, gk, delta = model.force_k(dk, post.lam_k, post.alpha, post.beta)
+    gk[0, 0, 0] = 0.0
+    got = {}
+    for fused in (True, False):
+        s = sampler_for(mk, eps=0.02, nsteps=4, seed=19)
+        s.set_plane_pass(fused)
+        s.set_coefficients(0, a32, b32)
+        s.set_state(0, d32)
+        st = s.state(0)
+        h = s.hamiltonian(0)
+        dH, acc = s.trajectory(0)
+        got[fused] = dict(st=st, data=h[2], dH=dH[0], after=s.state(0))
+        e_g = rel_l2(st["grad_k"], gk)
+        e_d = rel_l2(st["delta_r"], delta)
+        print(f"fused={fused}: gradient rel-L2 {e_g:.2e}, delta rel-L2 {e_d:.2e}, data energy "
+              f"{h[2]:.9e}, dH {dH[0]:.6e}", flush=True)
+        assert e_g < 1e-5 and e_d < 2e-6
+        s.close()
+    a, b = got[True], got[False]
+    assert rel_l2(a["st"]["grad_k"], b["st"]["grad_k"]) < 2e-6
+    assert abs(a["data"] - b["data"]) < 1e-9 * abs(b["data"]) + 1e-6
+    ref = hmc.trajectory(a["st"]["delta_k"].astype(np.complex128), post, 0.02, 4, 19, 0, 0)
+    for k in (True, False):
+        assert abs(got[k]["dH"] - ref["dH"]) < dh_tol(256)
+    assert rel_l2(a["after"]["mom_k"], b["after"]["mom_k"]) < 2e-6
+
+
+@pytest.mark.timeout(300)
 @pytest.mark.parametrize("launch", [0, -1])
 def test_batched_64_128_192_match_oracle(launch):
     """The batched workload's grid sizes (64^3, 128^3, 192^3, each with its own
