@@ -69,6 +69,17 @@ hmc_status cnn_gradient(cnn_ctx* ctx, int32_t n, const float* in3, const float* 
 hmc_status cnn_train_step(cnn_ctx* ctx, int32_t n, const float* in3, const float* target,
                           float lr, double* loss);
 
+/* The stored state of layer `layer` (0..3) from the last cnn_gradient or
+ * cnn_train_step, as float32 device arrays [N^3][C_out] (C_out = 16, or 2 for
+ * layer 3), any of which may be NULL: z the pre-activations (float32 sums
+ * plus bias), a the bfloat16 activations GELU(z) that feed the next layer (NULL
+ * for layer 3, which has none), dz the bfloat16 gradient of the loss with
+ * respect to z.  They let a test check one layer at a time from the layer's own
+ * inputs (the rounding points of the network are its bf16 weights, activations
+ * and output gradients).  HMC_EINVAL if no gradient was evaluated since the
+ * context was created, its grid size changed or cnn_forward ran. */
+hmc_status cnn_layer_state(cnn_ctx* ctx, int32_t layer, float* z, float* a, float* dz);
+
 const char* cnn_last_error(const cnn_ctx* ctx);
 void cnn_destroy(cnn_ctx* ctx);
 

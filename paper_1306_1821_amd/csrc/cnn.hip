@@ -45,9 +45,12 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
   return (uint16_t)(u >> 16);
 }
 __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
-__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.f + erff(z * 0.70710678118654752f)); }
+// GELU(z) = z Phi(z) with the normal CDF written as Phi(z) = erfc(-z / sqrt 2) / 2,
+// which keeps its relative accuracy in the lower tail (1 + erf(.) cancels there)
+__device__ __forceinline__ float norm_cdf(float z) { return 0.5f * erfcf(-z * 0.70710678118654752f); }
+__device__ __forceinline__ float gelu(float z) { return z * norm_cdf(z); }
 __device__ __forceinline__ float gelu_grad(float z) {
-  return 0.5f * (1.f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.3989422804014327f;
+  return norm_cdf(z) + z * expf(-0.5f * z * z) * 0.3989422804014327f;
 }
 
 // ------------------------------------------------------------------ kernels
@@ -359,6 +362,23 @@ __global__ void __launch_bounds__(256) k_wgrad_lds(int n, const uint16_t* __rest
   if (lane < 16) dbpart[gw * 16 + lane] = db;
 }
 
+// One layer's stored state in float32, [V][cout]: pre-activations (16-wide rows),
+// bf16 activations and bf16 pre-activation gradients (either pointer may be null).
+__global__ void __launch_bounds__(256) k_layer_state(long long nv, int cout,
+                                                     const float* __restrict__ z16,
+                                                     const uint16_t* __restrict__ a16,
+                                                     const uint16_t* __restrict__ dz16,
+                                                     float* __restrict__ z, float* __restrict__ a,
+                                                     float* __restrict__ dz) {
+  const long long tot = nv * cout;
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < tot; i += (long long)gridDim.x * 256) {
+    const long long v = i / cout, ch = i % cout;
+    if (z) z[i] = z16[v * 16 + ch];
+    if (a) a[i] = bf2f(a16[v * 16 + ch]);
+    if (dz) dz[i] = bf2f(dz16[v * 16 + ch]);
+  }
+}
+
 // Sum the per-wave partials of one layer into the flat gradient (fixed order).
 __global__ void __launch_bounds__(256) k_wreduce(const float* __restrict__ part,
                                                  const float* __restrict__ dbpart, int nw, int cin,
@@ -430,8 +450,13 @@ struct cnn_ctx {
   bf16x4* wd[4] = {nullptr, nullptr, nullptr, nullptr};
   int steps = 0;
   int n = 0;
+  bool grad_valid = false;  // the stored pre-activations and gradients belong to the last
+                            // cnn_gradient / cnn_train_step
   // activations for the current N
-  uint16_t *a0 = nullptr, *a[3] = {nullptr, nullptr, nullptr}, *dzA = nullptr, *dzB = nullptr;
+  uint16_t *a0 = nullptr, *a[3] = {nullptr, nullptr, nullptr};
+  // bf16 gradient of the loss with respect to each layer's pre-activations, one
+  // buffer per layer so that the last backward pass can be inspected
+  uint16_t* dz[4] = {nullptr, nullptr, nullptr, nullptr};
   float *z[4] = {nullptr, nullptr, nullptr, nullptr};
   float *wpart = nullptr, *dbpart = nullptr;
   double *lpart = nullptr, *lpart_h = nullptr;
@@ -471,9 +496,9 @@ void free_acts(cnn_ctx* c) {
   (void)hipFree(c->a0);
   for (int i = 0; i < 3; ++i) (void)hipFree(c->a[i]);
   for (int i = 0; i < 4; ++i) (void)hipFree(c->z[i]);
-  (void)hipFree(c->dzA);
-  (void)hipFree(c->dzB);
-  c->a0 = c->dzA = c->dzB = nullptr;
+  for (int i = 0; i < 4; ++i) (void)hipFree(c->dz[i]);
+  c->a0 = nullptr;
+  for (int i = 0; i < 4; ++i) c->dz[i] = nullptr;
   for (int i = 0; i < 3; ++i) c->a[i] = nullptr;
   for (int i = 0; i < 4; ++i) c->z[i] = nullptr;
   c->n = 0;
@@ -487,8 +512,7 @@ hmc_status ensure(cnn_ctx* c, int n) {
   CCHK(c, hipMalloc(&c->a0, nv * 4 * sizeof(uint16_t)));
   for (int i = 0; i < 3; ++i) CCHK(c, hipMalloc(&c->a[i], nv * 16 * sizeof(uint16_t)));
   for (int i = 0; i < 4; ++i) CCHK(c, hipMalloc(&c->z[i], nv * 16 * sizeof(float)));
-  CCHK(c, hipMalloc(&c->dzA, nv * 16 * sizeof(uint16_t)));
-  CCHK(c, hipMalloc(&c->dzB, nv * 16 * sizeof(uint16_t)));
+  for (int i = 0; i < 4; ++i) CCHK(c, hipMalloc(&c->dz[i], nv * 16 * sizeof(uint16_t)));
   c->n = n;
   return HMC_OK;
 }
@@ -524,14 +548,18 @@ hmc_status forward_t(cnn_ctx* c, int n, const float* in3) {
 }
 // forward for training (keeps the pre-activations) and for inference
 hmc_status forward(cnn_ctx* c, int n, const float* in3) { return forward_t<true>(c, n, in3); }
-hmc_status infer(cnn_ctx* c, int n, const float* in3) { return forward_t<false>(c, n, in3); }
+hmc_status infer(cnn_ctx* c, int n, const float* in3) {
+  c->grad_valid = false;  // overwrites the activations of the last gradient evaluation
+  return forward_t<false>(c, n, in3);
+}
 
 hmc_status gradient(cnn_ctx* c, int n, const float* in3, const float* target, double* loss) {
+  c->grad_valid = false;
   hmc_status st = forward(c, n, in3);
   if (st != HMC_OK) return st;
   const long long nv = (long long)n * n * n;
   const int blocks = (int)((nv / 16 + 3) / 4);
-  hipLaunchKernelGGL(k_loss, dim3(1024), dim3(256), 0, c->stream, nv, c->z[3], target, c->dzA,
+  hipLaunchKernelGGL(k_loss, dim3(1024), dim3(256), 0, c->stream, nv, c->z[3], target, c->dz[3],
                      c->lpart);
   const long long nchunks = nv / 16;
   const bool lds = n % kBZ == 0;
@@ -540,10 +568,9 @@ hmc_status gradient(cnn_ctx* c, int n, const float* in3, const float* target, do
   const int gblocks = lds ? std::min(nbricks, kWaves / 4) : 0;
   const int nw = lds ? 4 * gblocks : (int)((nchunks + cpw - 1) / cpw);
   const int wblocks = (nw + 3) / 4;
-  uint16_t* dz = c->dzA;
-  uint16_t* other = c->dzB;
   for (int l = 3; l >= 0; --l) {
     const uint16_t* ain = l == 0 ? c->a0 : c->a[l - 1];
+    const uint16_t* dz = c->dz[l];
     if (lds && l == 0)
       hipLaunchKernelGGL(k_wgrad_lds<4>, dim3(gblocks), dim3(256), 0, c->stream, n, ain, dz,
                          c->wpart, c->dbpart);
@@ -563,11 +590,10 @@ hmc_status gradient(cnn_ctx* c, int n, const float* in3, const float* target, do
       if (n % kBZ == 0)
         hipLaunchKernelGGL((k_conv_lds<C_DGRAD, true>), dim3((n / kBX) * (n / kBY) * (n / kBZ)),
                            dim3(256), 0, c->stream, n, dz, c->wd[l], nullptr, c->z[l - 1],
-                           nullptr, other);
+                           nullptr, c->dz[l - 1]);
       else
         hipLaunchKernelGGL((k_conv<16, C_DGRAD, 27, true>), dim3(blocks), dim3(256), 0,
-                           c->stream, n, dz, c->wd[l], nullptr, c->z[l - 1], nullptr, other);
-      std::swap(dz, other);
+                           c->stream, n, dz, c->wd[l], nullptr, c->z[l - 1], nullptr, c->dz[l - 1]);
     }
   }
   CCHK(c, hipGetLastError());
@@ -577,6 +603,7 @@ hmc_status gradient(cnn_ctx* c, int n, const float* in3, const float* target, do
   double s = 0.0;
   for (int i = 0; i < 1024; ++i) s += c->lpart_h[i];
   if (loss) *loss = s / (double)nv;
+  c->grad_valid = true;
   return HMC_OK;
 }
 
@@ -693,6 +720,16 @@ hmc_status cnn_gradient(cnn_ctx* c, int32_t n, const float* in3, const float* ta
     CCHK(c, hipMemcpyAsync(grad, c->g, n_params() * sizeof(float), hipMemcpyDeviceToHost, c->stream));
     CCHK(c, hipStreamSynchronize(c->stream));
   }
+  return HMC_OK;
+}
+
+hmc_status cnn_layer_state(cnn_ctx* c, int32_t layer, float* z, float* a, float* dz) {
+  if (!c || layer < 0 || layer > 3 || (layer == 3 && a)) return cfail(c, HMC_EINVAL, "bad argument");
+  if (c->n == 0 || !c->grad_valid) return cfail(c, HMC_EINVAL, "no cnn_gradient or cnn_train_step yet");
+  const long long nv = (long long)c->n * c->n * c->n;
+  hipLaunchKernelGGL(k_layer_state, dim3(4096), dim3(256), 0, c->stream, nv, kCout[layer],
+                     c->z[layer], layer < 3 ? c->a[layer] : nullptr, c->dz[layer], z, a, dz);
+  CCHK(c, hipGetLastError());
   return HMC_OK;
 }
 
