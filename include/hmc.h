@@ -175,6 +175,23 @@ hmc_status hamiltonian(hmc_ctx* ctx, int32_t chain, double* out);
  * sigma: host [n_bins] float64; n_modes: host [n_bins] int64 (may be NULL). */
 hmc_status shell_power(hmc_ctx* ctx, int32_t chain, double* sigma, int64_t* n_modes);
 
+/* shell_power for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same sigma_m and n_m, bit for bit, of a caller's half-complex field, with no
+ * context and no allocation.  delta_k: device [N][N][N/2+1] complex64 with
+ * N in {8, 16, 32, 64, 128, 192, 256}; n_bins in 1..128 (shells as above);
+ * sigma: device [n_bins] float64; n_modes: device [n_bins] int64 or NULL.
+ * Stream-ordered on `stream`, no synchronisation.  Its per-tile partial sums
+ * live in a library-owned device array of 1.06 MB (2 x 128 shells x 516 tiles
+ * of float64, enough for 256^3) that each GPU holds until the process ends and
+ * every call on that GPU shares: calls that overlap on one GPU (other streams,
+ * other threads) race on it.  Nothing needs clearing between calls (every
+ * partial the sums read is rewritten).  HMC_EINVAL on a null pointer or a size
+ * beyond these limits, HMC_EDEVICE on a HIP error; hmc_last_error(NULL)
+ * describes it. */
+hmc_status shell_power_noalloc(int32_t n, int32_t n_bins, const float* delta_k, double* sigma,
+                               int64_t* n_modes, void* stream);
+
 /* One block sweep (eq. multiblock): density HMC, P | delta, the joint move (if
  * rj_move), Nbar | delta, b, b | delta, Nbar, then alpha, beta, mass and
  * gradient are refreshed.  sweep_index (low 32 bits) selects every Philox

@@ -13,6 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhmc.so")
 
 HMC_OK = 0
+STATUS_EINVAL = -1
 STATUS = {0: "ok", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EUNSUPPORTED", -5: "ENUMERIC"}
 
 
@@ -48,7 +49,7 @@ EXPORTS = ["hmc_workspace_bytes", "hmc_init", "hmc_init_batch", "leapfrog_trajec
            "hmc_set_step", "hmc_warm_start", "hmc_set_launch", "hmc_set_plan", "hmc_get_launch",
            "hmc_autotune", "hmc_set_coefficients", "hmc_get_params", "hmc_shell_index",
            "hmc_set_mass", "hmc_set_mass_diagonal", "hmc_field_moments",
-           "hmc_timing", "hmc_use_graph", "hmc_last_error", "hmc_destroy",
+           "hmc_timing", "hmc_use_graph", "hmc_last_error", "hmc_destroy", "shell_power_noalloc",
            "hmc_set_plane_pass",
            "cnn_param_count", "cnn_create", "cnn_get_params", "cnn_forward", "cnn_gradient",
            "cnn_features", "cnn_layer_state",
@@ -104,6 +105,7 @@ def lib(path=LIB_PATH):
     L.hmc_last_error.restype = ctypes.c_char_p
     L.hmc_destroy.argtypes = [P]
     L.hmc_destroy.restype = None
+    L.shell_power_noalloc.argtypes = [I32, I32, P, P, P, P]
     F = ctypes.POINTER(ctypes.c_float)
     L.cnn_param_count.argtypes = []
     L.cnn_param_count.restype = ctypes.c_size_t
@@ -391,6 +393,26 @@ class Sampler:
         self.torch.cuda.synchronize(self.device)
         t = self.chains[chain]["t"]
         return {k: t[k].cpu().numpy() for k in ("delta_k", "mom_k", "grad_k", "delta_r", "alpha", "beta")}
+
+
+def shell_power_noalloc(delta_k, n_bins, sigma, n_modes=None, stream=None):
+    """sigma_m (and n_m) of a device half-complex field without a context or any
+    allocation (include/hmc.h): delta_k complex64 [N, N, N/2+1], sigma float64
+    [n_bins], n_modes int64 [n_bins] or None, all on the current device;
+    stream-ordered on `stream` (default: torch's current stream)."""
+    import torch
+    L = lib()
+    n = int(delta_k.shape[0])
+    assert delta_k.dtype == torch.complex64 and delta_k.is_contiguous()
+    assert sigma.dtype == torch.float64 and sigma.is_contiguous()
+    assert n_modes is None or (n_modes.dtype == torch.int64 and n_modes.is_contiguous())
+    st = torch.cuda.current_stream(delta_k.device) if stream is None else stream
+    r = L.shell_power_noalloc(n, int(n_bins), ctypes.c_void_p(delta_k.data_ptr()),
+                              ctypes.c_void_p(sigma.data_ptr()),
+                              ctypes.c_void_p(n_modes.data_ptr() if n_modes is not None else None),
+                              ctypes.c_void_p(st.cuda_stream))
+    if r != HMC_OK:
+        raise HmcError(r, L.hmc_last_error(None).decode())
 
 
 def _dptr_out(a):

@@ -13,8 +13,10 @@
 // alpha_i = sum_l b_l^2 Nbar_l R^l_i and beta_i = sum_l b_l (N^l_i - Nbar_l R^l_i)
 // are precomputed once per sweep.  The unitary normalisation N^(-3/2) is
 // applied in the x-pass (both directions).
+#include <mutex>
 #include <type_traits>
 
+#include "hmc.h"
 #include "kernels.hpp"
 #include "fft.hpp"
 #include "rng.hpp"
@@ -2603,3 +2605,95 @@ void launch_rj(int phase, const ChainDev* ch, int nch, int nb_max, hipStream_t s
 }
 
 }  // namespace hmc
+
+// ------------------------------------------------------------------ no-allocation shell sums
+// shell_power_noalloc: the shell sums of a caller's half-complex field without a
+// context.  Its per-tile partial sums live in `scratch`, a file-scope device array
+// (one copy per GPU, held until the process ends); host code reaches it only
+// through the address hipGetSymbolAddress returns for the current device.
+namespace hmc {
+namespace {
+constexpr int kNoAllocMaxN = 256;
+constexpr long long kNoAllocMaxModes = (long long)kNoAllocMaxN * kNoAllocMaxN * (kNoAllocMaxN / 2 + 1);
+constexpr int kNoAllocMaxTiles = (int)((kNoAllocMaxModes + kElemPerTile - 1) / kElemPerTile);
+// [shell][tile] sums of w |delta_hat|^2, then [tile][shell] mode counts
+constexpr size_t kScratchDoubles = 2 * (size_t)kMaxBins * kNoAllocMaxTiles;
+}  // namespace
+}  // namespace hmc
+
+static __device__ __align__(256) double scratch[hmc::kScratchDoubles];
+
+namespace hmc {
+namespace {
+
+__global__ void __launch_bounds__(kWideThreads) k_shell_power_field(const float2* __restrict__ dk,
+                                                                    int n, int nb, long long nh,
+                                                                    int ntiles, double* part) {
+  __shared__ double bins[kShellWaves * kMaxBins];
+  __shared__ double cnt[kShellWaves * kMaxBins];
+  double* cpart = part + (size_t)kMaxBins * ntiles;
+  for (int lt = blockIdx.x; lt < ntiles; lt += gridDim.x)
+    shell_sum_tile<SP_POWER>(dk, nullptr, n, nb, nh, lt, part + lt, (size_t)ntiles,
+                             cpart + (size_t)lt * nb, bins, cnt);
+}
+
+// block (q, 0): sigma_q from the [shell][tile] row; block (q, 1): n_q from the
+// [tile][shell] column; the same fixed order as the context's column sums
+__global__ void __launch_bounds__(kThreads) k_shell_power_cols(const double* __restrict__ part,
+                                                               int nb, int ntiles,
+                                                               double* __restrict__ sigma,
+                                                               int64_t* __restrict__ n_modes) {
+  __shared__ double red[4];
+  const int q = blockIdx.x;
+  if (blockIdx.y == 0) {
+    const double s = column_sum(part + (size_t)q * ntiles, 1, ntiles, red);
+    if (threadIdx.x == 0) sigma[q] = s;
+  } else {
+    const double s = column_sum(part + (size_t)kMaxBins * ntiles + q, (size_t)nb, ntiles, red);
+    if (threadIdx.x == 0) n_modes[q] = (int64_t)s;
+  }
+}
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {};  // device address of `scratch` per device id
+
+}  // namespace
+}  // namespace hmc
+
+extern "C" hmc_status shell_power_noalloc(int32_t n, int32_t n_bins, const float* delta_k,
+                                          double* sigma, int64_t* n_modes, void* stream) {
+  using namespace hmc;
+  if (!delta_k || !sigma) return record_free_error(HMC_EINVAL, "shell_power_noalloc: null pointer");
+  if (!(n == 8 || n == 16 || n == 32 || n == 64 || n == 128 || n == 192 || n == 256))
+    return record_free_error(HMC_EINVAL, "shell_power_noalloc: N must be 8, 16, 32, 64, 128, 192 or 256");
+  if (n_bins < 1 || n_bins > kMaxBins)
+    return record_free_error(HMC_EINVAL, "shell_power_noalloc: n_bins must be in 1..128");
+  const long long nh = (long long)n * n * (n / 2 + 1);
+  const int ntiles = (int)((nh + kElemPerTile - 1) / kElemPerTile);
+  if (ntiles > kNoAllocMaxTiles)  // cannot happen for N <= 256; kept with the size checks
+    return record_free_error(HMC_EINVAL, "shell_power_noalloc: grid exceeds the scratch array");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+    return record_free_error(HMC_EDEVICE, "shell_power_noalloc: no current device");
+  void* ptr = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+      const hipError_t e = hipGetSymbolAddress(&g_scratch_ptr[dev], HIP_SYMBOL(scratch));
+      if (e != hipSuccess) {
+        g_scratch_ptr[dev] = nullptr;
+        return record_free_error(HMC_EDEVICE, "shell_power_noalloc: hipGetSymbolAddress failed");
+      }
+    }
+    ptr = g_scratch_ptr[dev];
+  }
+  hipStream_t s = (hipStream_t)stream;
+  double* part = (double*)ptr;
+  hipLaunchKernelGGL(k_shell_power_field, dim3(eg(ntiles)), dim3(kWideThreads), 0, s,
+                     (const float2*)delta_k, n, n_bins, nh, ntiles, part);
+  hipLaunchKernelGGL(k_shell_power_cols, dim3(n_bins, n_modes ? 2 : 1), dim3(kThreads), 0, s, part,
+                     n_bins, ntiles, sigma, n_modes);
+  if (hipGetLastError() != hipSuccess)
+    return record_free_error(HMC_EDEVICE, "shell_power_noalloc: launch failed");
+  return HMC_OK;
+}

@@ -4,6 +4,8 @@
 
 namespace hmc {
 
+// records a context-free failure for hmc_last_error(NULL) and returns st
+int32_t record_free_error(int32_t st, const char* why);
 
 // x-pass modes (k-space side of a leapfrog step; see kernels.hip)
 enum XMode : int { X_INV = 0, X_FWD = 1, X_START = 2, X_STEP = 3, X_END = 4 };

@@ -149,6 +149,13 @@ struct hmc_ctx {
     }                                                                       \
   } while (0)
 
+namespace hmc {
+int32_t record_free_error(int32_t st, const char* why) {
+  g_err = why;
+  return st;
+}
+}  // namespace hmc
+
 static hmc_status fail(hmc_ctx* ctx, hmc_status st, const std::string& why) {
   if (ctx) ctx->err = why;
   g_err = why;

@@ -93,3 +93,15 @@ def test_null_arguments(L):
 def test_cnn_parameter_count(L):
     assert L.cnn_param_count() == sum(27 * ci * co + co for ci, co in binding.CNN_LAYERS) == 16034
 
+
+def test_shell_power_noalloc_rejects_bad_arguments_on_the_host(L):
+    """Argument checks come before any device call (no GPU needed)."""
+    buf = (ctypes.c_double * 4)()
+    assert L.shell_power_noalloc(32, 16, None, buf, None, None) == binding.STATUS_EINVAL
+    assert b"null" in L.hmc_last_error(None)
+    dummy = ctypes.c_void_p(1)   # never dereferenced: the size checks fail first
+    assert L.shell_power_noalloc(48, 16, dummy, buf, None, None) == binding.STATUS_EINVAL
+    assert b"N must be" in L.hmc_last_error(None)
+    assert L.shell_power_noalloc(32, 0, dummy, buf, None, None) == binding.STATUS_EINVAL
+    assert L.shell_power_noalloc(32, 129, dummy, buf, None, None) == binding.STATUS_EINVAL
+    assert b"n_bins" in L.hmc_last_error(None)
