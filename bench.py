@@ -427,6 +427,65 @@ def learned_main(args):
     print(json.dumps(out), flush=True)
 
 
+def learned_rhat_main(args):
+    """Learned vs plain mass P(k) ESS/s at equal convergence: split R-hat < 1.01 on
+    the data-dominated shells, 4 chains per arm.  The network is trained as for
+    --learned on 128^3 mocks; it is applied to the held-out 128^3 survey (mock seed 0,
+    not among the training seeds) and to the 256^3 survey, each arm sampling until
+    the target or --rhat-seconds of sampling per arm."""
+    import torch
+    from paper_1306_1821_amd import learned
+    from paper_1306_1821_amd.binding import CNN
+    from synth import CONFIGS, make_mock
+
+    log = lambda m: print(f"[learned-rhat] {m}", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    net = CNN(learned.init_params(3))
+    mocks = learned.mock_series(CONFIGS["cfg2"], range(100, 100 + args.mocks))
+    ins, tg, own = learned.make_training_set(net, mocks, per_batch=8, burn=20, samples=31, thin=8,
+                                             eps=0.035, log=log)
+    del mocks
+    losses = learned.train(net, ins, tg, own, args.train_steps, lr=2e-3, log=log, log_every=1000)
+    del ins, tg
+    torch.cuda.empty_cache()
+    t_prep = time.perf_counter() - t0
+    out = {"metric": "P(k) ESS/s learned-mass vs plain at equal split R-hat < 1.01",
+           "unit": "effective P(k) samples/s (median over data-dominated shells)",
+           "n_gpus": 1, "dtype": "f32", "data": "synthetic", "higher_is_better": True,
+           "training": {"draws": int(len(own)), "steps": args.train_steps,
+                        "final_loss": float(losses[-200:].mean()), "seconds": t_prep},
+           "rhat_seconds_per_arm": args.rhat_seconds, "sizes": {}}
+    for name in args.rhat_workloads.split(","):
+        mk = make_mock(CONFIGS[name], dtype=np.float32)
+        s = learned.start_chains(mk, 1)
+        x = learned.survey_inputs(net, s, 0, mk)
+        s.close()
+        mu, lv = net.forward(x)
+        dd = learned.data_dominated_shells(mk)
+        log(f"{name}: N={mk['cfg'].n}, {len(dd)} data-dominated shells")
+        arms = tuple((a, a == "learned") for a in args.rhat_arms.split(","))
+        r = learned.equal_rhat_study(mk, mu, lv, dd, chains=4, burn=200, block=500,
+                                     max_seconds=args.rhat_seconds, eps0=args.eps, log=log,
+                                     arms=arms)
+        row = {}
+        for arm, v in r.items():
+            t = learned.ess_table(v, dd)
+            row[arm] = dict(eps=v["eps"], acceptance=v["acceptance"], ms_per_sweep=v["ms_per_sweep"],
+                            tune_acceptance=v["tune_acceptance"],
+                            sweeps=v["sweeps"], reached=v["reached"], max_rhat=v["max_rhat"],
+                            sweeps_to_target=v["sweeps_to_target"],
+                            seconds_to_target=v["seconds_to_target"],
+                            median_ess_per_s=t["median_ess_per_s"], min_ess_per_s=t["min_ess_per_s"],
+                            history=v["history"])
+        if "learned" in row and "plain" in row:
+            row["ratio_median_ess_per_s"] = (row["learned"]["median_ess_per_s"]
+                                             / max(1e-30, row["plain"]["median_ess_per_s"]))
+        out["sizes"][name] = row
+        del mu, lv
+        torch.cuda.empty_cache()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -441,6 +500,12 @@ def main():
                     help="cfg4: total sweeps (timed + untimed) for the R-hat across chains")
     ap.add_argument("--learned", action="store_true",
                     help="learned warm start / mass comparison (steps = measured sweeps per mass)")
+    ap.add_argument("--learned-rhat", action="store_true",
+                    help="learned vs plain mass ESS/s at equal split R-hat < 1.01")
+    ap.add_argument("--rhat-seconds", type=float, default=600.0,
+                    help="--learned-rhat: sampling seconds per arm and size at most")
+    ap.add_argument("--rhat-workloads", default="cfg2,cfg3")
+    ap.add_argument("--rhat-arms", default="plain,learned")
     ap.add_argument("--mocks", type=int, default=64)
     ap.add_argument("--train-steps", type=int, default=4000)
     ap.add_argument("--burn-sweeps", type=int, default=300)
@@ -468,6 +533,8 @@ def main():
         return ablation_main(args)
     if args.posterior:
         return posterior_main(args)
+    if args.learned_rhat:
+        return learned_rhat_main(args)
     if args.learned:
         if args.steps == 20:
             args.steps = 1500

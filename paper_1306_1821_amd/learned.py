@@ -324,3 +324,58 @@ def ess_study(mk, mu, lv, chains=4, burn=100, sweeps=600, target=0.8, eps0=None,
                 f"{int((r['rhat'] < 1.01).sum())}/{len(r['rhat'])}; data-dominated shells: {dd}")
     return out
 
+
+
+def equal_rhat_study(mk, mu, lv, shells, chains=4, burn=200, block=500, max_seconds=600.0,
+                     rhat_target=1.01, target=0.8, eps0=None, seed=21, log=None,
+                     arms=(("plain", False), ("learned", True))):
+    """P(k) efficiency of the plain and the learned mass at equal convergence.
+
+    Each arm: `chains` chains warm-started from (mu, lv) with different draws, eps
+    tuned to the same acceptance, `burn` sweeps dropped, then blocks of `block`
+    sweeps until the rank-normalised split R-hat of ln P is below `rhat_target` on
+    every shell in `shells` over the whole window after burn-in, or `max_seconds`
+    of sampling have passed.  ESS/s is the bulk ESS of that window over its wall
+    time (Sec. "Testing burn-in and statistical efficiency" measures efficiency by
+    the autocorrelation of eq. CORR_COEFF; the bulk ESS sums it).  An arm that
+    does not reach the target reports the R-hat it reached and the sweeps the
+    target would take, from R-hat - 1 falling as 1 / ESS, i.e. as 1 / sweeps."""
+    shells = np.asarray(shells)
+    out = {}
+    for name, learned_mass in arms:
+        s = start_chains(mk, chains, "draw", mu, lv, lv if learned_mass else None, eps0, seed)
+        # ten rounds of 16 trajectories: both arms end near the target acceptance
+        eps, rate = tune_step(s, eps0 if eps0 is not None else mk["cfg"].eps, target=target,
+                              rounds=10, trajs=16)
+        for i in range(chains):
+            s.warm_start(i, mu, lv, draw_index=i)
+        run_chains(s, burn)
+        parts, accs, wall, sweeps, history = [], [], 0.0, 0, []
+        while True:
+            pk, acc, w, _ = run_chains(s, block, first_sweep=burn + sweeps)
+            parts.append(pk)
+            accs.append(acc)
+            wall += w
+            sweeps += block
+            trace = np.concatenate(parts, axis=1)
+            rh = np.array([diagnostics.split_rhat(np.log(trace[:, :, m])) for m in shells])
+            history.append((sweeps, float(rh.max())))
+            if log:
+                log(f"{name}: {sweeps} sweeps, {wall:.0f} s, max split R-hat {rh.max():.4f}")
+            if rh.max() < rhat_target or wall > max_seconds:
+                break
+        s.close()
+        r = pk_ess_summary(trace, wall)
+        reached = bool(rh.max() < rhat_target)
+        need = sweeps if reached else int(np.ceil(sweeps * (rh.max() - 1.0) / (rhat_target - 1.0)))
+        r.update(eps=eps, tune_acceptance=rate, acceptance=float(np.concatenate(accs).mean()),
+                 ms_per_sweep=1e3 * wall / sweeps, sweeps=sweeps, reached=reached,
+                 max_rhat=float(rh.max()), sweeps_to_target=need,
+                 seconds_to_target=need * wall / sweeps, history=history)
+        out[name] = r
+        if log:
+            t = ess_table(r, shells)
+            log(f"{name}: eps {eps:.4f}, acceptance {r['acceptance']:.2f}, {r['ms_per_sweep']:.1f} ms/sweep, "
+                f"R-hat {r['max_rhat']:.4f} after {sweeps} sweeps ({'reached' if reached else 'not reached'}; "
+                f"target at ~{need} sweeps), ESS/s median {t['median_ess_per_s']:.3g} min {t['min_ess_per_s']:.3g}")
+    return out
