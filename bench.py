@@ -47,16 +47,17 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_bench_256.md")
 KERNELS_SRC = os.path.join(ROOT, "paper_1306_1821_amd", "csrc", "kernels.hip")
 
 
-def measured_traffic():
-    """HBM bytes per X_STEP launch from the committed FETCH_SIZE / WRITE_SIZE
-    summary, or None when the kernel source has changed since it was taken."""
+def measured_traffic(kind="x-step"):
+    """HBM bytes per launch of the k-space step pass (kind "x-step") or of the y-z
+    plane pass ("plane") from the committed FETCH_SIZE / WRITE_SIZE summary, or None
+    when the kernel source has changed since it was taken."""
     import hashlib
     import re
     try:
         text = open(TRAFFIC_FILE).read()
     except OSError:
         return None
-    b = re.search(r"x-step traffic per launch \(bytes\): (\d+)", text)
+    b = re.search(re.escape(kind) + r" traffic per launch \(bytes\): (\d+)", text)
     h = re.search(r"kernels.hip sha256: ([0-9a-f]{64})", text)
     if not b or not h:
         return None
@@ -555,7 +556,8 @@ def main():
         s.sweep(sweep)
         sweep += 1
     torch.cuda.synchronize()
-    s.timing(0x411)                     # HIP events around every 5th k-space step pass
+    # HIP events around every 5th k-space step pass and every 5th real-space / plane pass
+    s.timing(0x10 | 0x1 | 0x4 | (4 << 8))
     acc, rj_acc = [], []
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -596,9 +598,21 @@ def main():
 
     steps = args.steps * spec["nsteps"]
     value = steps / dt
-    avg_ms = ms[0] / max(1, launches[0])
-    bytes_launch = 6 * nh * 8          # read T, delta_hat, p_hat; write delta_hat, p_hat, T
-    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
+    plane = launches_all[1] < launches_all[2]     # the fused y-z plane pass ran
+    # k-space step pass: read T, delta_hat, p_hat; write delta_hat, p_hat, T
+    x_ms, x_bytes = ms[0] / max(1, launches[0]), 6 * nh * 8
+    # plane pass (or z pass): read T, alpha, beta; write T
+    z_ms, z_bytes = ms[2] / max(1, launches[2]), 2 * nh * 8 + 2 * n ** 3 * 4
+    roof_x = {"bound": "hbm", "achieved": x_bytes / (x_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+              "unit": "GB/s", "frac": x_bytes / (x_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+              "traffic": measured_traffic("x-step") if args.workload == "cfg3" else None,
+              "kernel": f"k_xpass_n<{n}, X_STEP>", "avg_ms": x_ms, "launches": int(launches[0]),
+              "bytes_per_launch": x_bytes}
+    roof_p = {"bound": "hbm", "achieved": z_bytes / (z_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+              "unit": "GB/s", "frac": z_bytes / (z_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+              "traffic": measured_traffic("plane") if args.workload == "cfg3" else None,
+              "kernel": f"k_yzpass_n<{n}>", "avg_ms": z_ms, "launches": int(launches[2]),
+              "bytes_per_launch": z_bytes}
     out = {
         "metric": f"leapfrog steps/s at {n}^3",
         "value": value,
@@ -617,11 +631,10 @@ def main():
                                f"{spec['nsteps']} leapfrog steps, joint move "
                                f"{'on' if spec['rj'] else 'off'}; one bench step = one sweep",
                    "eps": spec["eps"]},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic() if args.workload == "cfg3" else None,
-                     "kernel": f"k_xpass_n<{n}, X_STEP>", "avg_ms": avg_ms,
-                     "launches": int(launches[0]), "bytes_per_launch": bytes_launch},
+        # the dominant kernel by GPU time: the plane pass where it runs (two of them per
+        # sweep step, density and joint move), else the k-space step pass
+        "roofline": roof_p if plane else roof_x,
+        "roofline_kspace_step": roof_x,
         "acceptance": float(np.mean(acc)),
         "rj_acceptance": float(np.mean(rj_acc)),
         "trajectory_leapfrog_steps_per_s": ntraj * spec["nsteps"] / dt_traj,

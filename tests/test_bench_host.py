@@ -30,10 +30,14 @@ def test_traffic_figure_follows_the_kernel_source(tmp_path, monkeypatch):
     recorded = re.search(r"kernels.hip sha256: ([0-9a-f]{64})", text).group(1)
     current = hashlib.sha256(open(bench.KERNELS_SRC, "rb").read()).hexdigest()
     got = bench.measured_traffic()
+    plane = bench.measured_traffic("plane")
     if current == recorded:
         assert isinstance(got, int) and 0.99 < got / (6 * 256 * 256 * 129 * 8) < 1.2
+        if "plane traffic per launch (bytes):" in text:
+            algorithmic = 2 * 256 * 256 * 129 * 8 + 2 * 256 ** 3 * 4
+            assert isinstance(plane, int) and 0.99 < plane / algorithmic < 1.3
     else:                                  # summary older than the source: no figure
-        assert got is None
+        assert got is None and plane is None
     other = tmp_path / "kernels.hip"
     other.write_text(open(bench.KERNELS_SRC).read() + "\n// changed\n")
     monkeypatch.setattr(bench, "KERNELS_SRC", str(other))
