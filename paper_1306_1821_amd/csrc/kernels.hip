@@ -1170,20 +1170,26 @@ __device__ __forceinline__ void yzpass(const ChainDev& d, int x, const ZArgs a, 
   float* drout = (a.flags & ZF_WRITE_DRN) ? d.drn : (a.flags & ZF_WRITE_DR) ? d.dr : nullptr;
   float2* const Lr = lds + r * RSZ;  // this thread's row of the chunk buffer
   double dat = 0.0;
+  // alpha and beta of chunk q + 1 are loaded as soon as chunk q's force is formed,
+  // so that they arrive while chunk q finishes its transforms
+  float2 al[EZ], be[EZ];
+  auto load_ab = [&](int q) {
+    const size_t rq = ((size_t)x * N + q * RZ) * M;  // the chunk's first voxel pair (uniform)
+    const float2* ab = ap + rq;
+    const float2* bb = bp + rq;
+    asm volatile("" : "+s"(ab), "+s"(bb));  // scalar bases, one offset register (see at())
+#pragma unroll
+    for (int e = 0; e < EZ; ++e) {
+      al[e] = ld_si(ab + TZ * e, (uint32_t)(r * M + tz));
+      be[e] = ld_si(bb + TZ * e, (uint32_t)(r * M + tz));
+    }
+  };
+  load_ab(0);
   static_for<0, NCH>([&](auto qc) {
     constexpr int q = decltype(qc)::value;
     const size_t rq = ((size_t)x * N + q * RZ) * M;   // the chunk's first voxel pair (uniform)
     const uint32_t ro = (uint32_t)(r * M + tz);        // this thread's pair in the chunk
     float2* const Lsr = Ls + (q * RZ + r) * LS - CR;   // this row's columns CR.. in LDS
-    const float2* ab = ap + rq;
-    const float2* bb = bp + rq;
-    asm volatile("" : "+s"(ab), "+s"(bb));  // scalar bases, one offset register (see at())
-    float2 al[EZ], be[EZ];
-#pragma unroll
-    for (int e = 0; e < EZ; ++e) {
-      al[e] = ld_si(ab + TZ * e, ro);
-      be[e] = ld_si(bb + TZ * e, ro);
-    }
     __syncthreads();  // the buffer's previous readers are done
 #pragma unroll
     for (int g = 0; g < GR; ++g)
@@ -1208,6 +1214,7 @@ __device__ __forceinline__ void yzpass(const ChainDev& d, int x, const ZArgs a, 
                (0.5 * al[e].y * xv.y - be[e].y) * (double)xv.y;
       w[e] = make_float2(al[e].x * xv.x - be[e].x, al[e].y * xv.y - be[e].y);
     }
+    if constexpr (q + 1 < NCH) load_ab(q + 1);
     zfft_dtw<M, TZ, +1, typename C::RLZ>(w, Lr, tz, true, twM);
     float x0 = 0.f;
     r2c_post<N, TZ, EZ>(w, Lr, tz, true, twN, [&](int k, float2 X) {
