@@ -1075,7 +1075,16 @@ template <> struct PC<256> {
   using RLZ = Radices<8, 4, 4>;          // the half-length (128-point) complex transform
   static constexpr int GL = 1;           // pencil groups that wait in LDS instead of registers
 };
-template <int N> constexpr bool has_plane() { return N == 256; }
+// 128^3: the plane (128 x 65 complex, 66 KB) in registers of 512 threads (16 values
+// each, no group in LDS); 8-thread z rows of the 64-point half-length transform
+template <> struct PC<128> {
+  static constexpr int P = 512;
+  static constexpr int TY = 16;          // 8 values each
+  using RLY = Radices<8, 4, 4>;
+  static constexpr int TZ = 8;           // 8 values each
+  using RLZ = Radices<8, 8>;
+  static constexpr int GL = 0;
+};
 // LDS layout in float2: [0, A) the y-transform exchange and the z-row chunk buffer
 // (used in turn), [A, A + N LS) the columns kept in LDS (row-major, stride LS),
 // then N values for separating column 0
@@ -1293,10 +1302,12 @@ __global__ void __launch_bounds__(PC<N>::P) k_yzpass_n(const ChainDev* __restric
   yzpass<N>(ch[blockIdx.x / N], (int)(blockIdx.x % N), a, lds, stw, red);
 }
 
-bool plane_pass_supported(int n) { return n == 256; }
+bool plane_pass_supported(int n) { return n == 128 || n == 256; }
 void launch_yzpass(const ChainDev* ch, int nch, ZArgs a, const float2* tw, hipStream_t s, int n) {
   if (n == 256)
     hipLaunchKernelGGL(k_yzpass_n<256>, dim3(nch * 256), dim3(PC<256>::P), 0, s, ch, a, tw);
+  else if (n == 128)
+    hipLaunchKernelGGL(k_yzpass_n<128>, dim3(nch * 128), dim3(PC<128>::P), 0, s, ch, a, tw);
 }
 
 // ------------------------------------------------------------------ learned mass

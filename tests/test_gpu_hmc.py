@@ -185,13 +185,15 @@ def test_batched_mixed_sizes_match_oracle():
 
 
 @pytest.mark.timeout(300)
-def test_plane_pass_matches_separate_passes_and_oracle():
-    """At 256^3 the gradient evaluations run the fused y-z plane pass (inverse y,
-    C2R z, data force, R2C z, forward y with the plane on chip; the kz = 0 and
-    kz = N/2 columns travel as one complex column).  Against the separate y, z, y
-    passes and against the oracle: the gradient of set_state, the data energy,
-    the real field, and a trajectory's end point and dH."""
-    mk = mock("cfg3")
+@pytest.mark.parametrize("case,eps,nsteps", [("cfg3", 0.02, 4), ("cfg2", 0.04, 8)])
+def test_plane_pass_matches_separate_passes_and_oracle(case, eps, nsteps):
+    """At 256^3 and 128^3 the gradient evaluations run the fused y-z plane pass
+    (inverse y, C2R z, data force, R2C z, forward y with the plane on chip; the
+    kz = 0 and kz = N/2 columns travel as one complex column).  Against the
+    separate y, z, y passes and against the oracle: the gradient of set_state, the
+    data energy, the real field, and a trajectory's end point and dH."""
+    mk = mock(case)
+    n = mk["cfg"].n
     a32, b32 = coefficients32(mk)
     d32, dk = start_state(mk)
     post = oracle_posterior(mk, a32, b32, workers=16)
@@ -199,7 +201,7 @@ def test_plane_pass_matches_separate_passes_and_oracle():
     gk[0, 0, 0] = 0.0
     got = {}
     for fused in (True, False):
-        s = sampler_for(mk, eps=0.02, nsteps=4, seed=19)
+        s = sampler_for(mk, eps=eps, nsteps=nsteps, seed=19)
         s.set_plane_pass(fused)
         s.set_coefficients(0, a32, b32)
         s.set_state(0, d32)
@@ -216,9 +218,9 @@ def test_plane_pass_matches_separate_passes_and_oracle():
     a, b = got[True], got[False]
     assert rel_l2(a["st"]["grad_k"], b["st"]["grad_k"]) < 2e-6
     assert abs(a["data"] - b["data"]) < 1e-9 * abs(b["data"]) + 1e-6
-    ref = hmc.trajectory(a["st"]["delta_k"].astype(np.complex128), post, 0.02, 4, 19, 0, 0)
+    ref = hmc.trajectory(a["st"]["delta_k"].astype(np.complex128), post, eps, nsteps, 19, 0, 0)
     for k in (True, False):
-        assert abs(got[k]["dH"] - ref["dH"]) < dh_tol(256)
+        assert abs(got[k]["dH"] - ref["dH"]) < dh_tol(n)
     assert rel_l2(a["after"]["mom_k"], b["after"]["mom_k"]) < 2e-6
 
 
