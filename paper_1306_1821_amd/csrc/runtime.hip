@@ -258,12 +258,31 @@ struct Seq {
     tm.done(s);
   }
   // inverse y transforms, the real-space data force (C2R z, alpha delta - beta,
-  // R2C z) and forward y transforms: one fused plane pass for single-size
-  // contexts of a grid size that has one, else three passes
+  // R2C z) and forward y transforms: one fused plane pass for grid sizes that have
+  // one (the whole context, or each size group of a batch whose y and real-space
+  // passes run one launch per size group), else three passes
   void yz(int zflags) {
+    const ZArgs za{zflags, 0, nullptr};
     if (c->plane_pass && un != 0 && plane_pass_supported(un)) {
       Timed tm(c, 2, s);
-      launch_yzpass(d, nch, ZArgs{zflags, 0, nullptr}, c->tw, s, un);
+      launch_yzpass(d, nch, za, c->tw, s, un);
+      tm.done(s);
+      return;
+    }
+    bool some = false;
+    for (auto& g : c->groups) some |= plane_pass_supported(g.n);
+    if (c->plane_pass && un == 0 && c->grouped[1] && c->grouped[2] && some) {
+      Timed tm(c, 2, s);
+      for (auto& g : c->groups) {
+        if (plane_pass_supported(g.n)) {
+          launch_yzpass(g.d, g.nch, za, c->tw, s, g.n);
+        } else {
+          launch_ypass(-1, g.d, g.nch, g.total[kTileXY], c->lds_x, c->tw, 0, s, g.n, 0, c->plan[1]);
+          launch_zpass(Z_GRAD, g.d, g.nch, g.total[kTileZ], c->lds_z, za, c->tw, 0, s, g.n,
+                       c->plan[2]);
+          launch_ypass(+1, g.d, g.nch, g.total[kTileXY], c->lds_x, c->tw, 0, s, g.n, 0, c->plan[1]);
+        }
+      }
       tm.done(s);
       return;
     }
