@@ -137,6 +137,30 @@ def test_trajectory_matches_oracle(case, eps, nsteps):
     s.close()
 
 
+def test_trajectories_from_zero_match_oracle():
+    """The end-to-end case of the float32-state analysis: 8^3, eps 0.05, 20 steps,
+    every trajectory started at delta = 0 with its own momentum draw."""
+    mk = mock("tiny8x2")
+    n = mk["cfg"].n
+    a32, b32 = coefficients32(mk)
+    s = sampler_for(mk, eps=0.05, nsteps=20, seed=17)
+    s.set_coefficients(0, a32, b32)
+    post = oracle_posterior(mk, a32, b32, workers=4)
+    diffs = []
+    for traj in range(16):
+        s.set_state(0, np.zeros((n, n, n), np.float32))
+        before = s.state(0)
+        assert not before["delta_k"].any()
+        dH, acc = s.trajectory(traj)
+        ref = hmc.trajectory(before["delta_k"].astype(np.complex128), post, 0.05, 20, 17, 0, traj)
+        diffs.append(abs(dH[0] - ref["dH"]))
+        if abs(ref["log_u"] + ref["dH"]) > dh_tol(n):
+            assert bool(acc[0]) == ref["accepted"]
+    print(f"|dH diff| from delta = 0: median {np.median(diffs):.2e}, max {max(diffs):.2e}")
+    assert max(diffs) < dh_tol(n)
+    s.close()
+
+
 @pytest.mark.parametrize("eps,accepted", [(0.02, True), (0.8, False)])
 def test_gradient_cache_after_trajectory(eps, accepted):
     """After a trajectory, accepted (small step) or rejected (eps = 0.8: dH of 50-70 in
