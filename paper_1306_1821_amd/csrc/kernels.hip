@@ -1075,6 +1075,17 @@ template <> struct PC<256> {
   using RLZ = Radices<8, 4, 4>;          // the half-length (128-point) complex transform
   static constexpr int GL = 1;           // pencil groups that wait in LDS instead of registers
 };
+// 192^3: the plane (192 x 97 complex, 149 KB) in registers of 512 threads (36 values
+// each, no group in LDS); radix-12 pencils, 8-thread z rows of the 96-point
+// half-length transform (12 values each)
+template <> struct PC<192> {
+  static constexpr int P = 512;
+  static constexpr int TY = 16;          // 12 values each
+  using RLY = Radices<4, 4, 12>;
+  static constexpr int TZ = 8;           // 12 values each
+  using RLZ = Radices<4, 4, 6>;
+  static constexpr int GL = 0;
+};
 // 128^3: the plane (128 x 65 complex, 66 KB) in registers of 512 threads (16 values
 // each, no group in LDS); 8-thread z rows of the 64-point half-length transform
 template <> struct PC<128> {
@@ -1262,7 +1273,7 @@ __device__ __forceinline__ void yzpass(const ChainDev& d, int x, const ZArgs a, 
 #pragma unroll
           for (int e = 0; e < EY; ++e) {
             const int k = t + TY * e;
-            const float2 z = v[0][e], zc = cconj(Lu[(N - k) & (N - 1)]);
+            const float2 z = v[0][e], zc = cconj(Lu[(N - k) % N]);  // N need not be a power of two
             const float2 df = csub(z, zc);
             v[0][e] = make_float2(0.5f * (z.x + zc.x), 0.5f * (z.y + zc.y));
             cb[e] = make_float2(0.5f * df.y, -0.5f * df.x);
@@ -1302,10 +1313,12 @@ __global__ void __launch_bounds__(PC<N>::P) k_yzpass_n(const ChainDev* __restric
   yzpass<N>(ch[blockIdx.x / N], (int)(blockIdx.x % N), a, lds, stw, red);
 }
 
-bool plane_pass_supported(int n) { return n == 128 || n == 256; }
+bool plane_pass_supported(int n) { return n == 128 || n == 192 || n == 256; }
 void launch_yzpass(const ChainDev* ch, int nch, ZArgs a, const float2* tw, hipStream_t s, int n) {
   if (n == 256)
     hipLaunchKernelGGL(k_yzpass_n<256>, dim3(nch * 256), dim3(PC<256>::P), 0, s, ch, a, tw);
+  else if (n == 192)
+    hipLaunchKernelGGL(k_yzpass_n<192>, dim3(nch * 192), dim3(PC<192>::P), 0, s, ch, a, tw);
   else if (n == 128)
     hipLaunchKernelGGL(k_yzpass_n<128>, dim3(nch * 128), dim3(PC<128>::P), 0, s, ch, a, tw);
 }
