@@ -124,7 +124,10 @@ def oracle_step_ms(mk, spec, workers, reps=5):
 
 def gpu_step_ms(mk, spec, ntraj=20):
     """Wall time per leapfrog step of bare trajectories, and the summed device
-    time of the four passes of one step (x, y twice, z) from HIP events."""
+    time of one step's passes from HIP events: the k-space pass, the y-z plane
+    pass (or the real-space pass) and the y passes in the number launched per
+    gradient (two in the four-pass form; with the plane pass only the momentum
+    draw's one per trajectory, spread over its steps)."""
     import torch
     from paper_1306_1821_amd.binding import Sampler
     s = Sampler([spec])
@@ -143,7 +146,7 @@ def gpu_step_ms(mk, spec, ntraj=20):
     ms, launches = s.timing(0)
     s.close()
     per = [ms[j] / max(1, launches[j]) for j in range(3)]
-    return wall, per[0] + 2.0 * per[1] + per[2]
+    return wall, per[0] + per[1] * launches[1] / max(1, launches[2]) + per[2]
 
 
 def oracle_timing_main(args):
