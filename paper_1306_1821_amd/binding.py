@@ -358,7 +358,8 @@ class Sampler:
         self._check(self.L.hmc_set_plan(self.ctx, int(pass_class), int(plan)))
 
     def set_plane_pass(self, enable=True):
-        """Fused y-z plane pass (256^3 single-size contexts) or separate y, z, y passes."""
+        """Fused y-z plane pass (grid sizes 128, 192, 256: single-size contexts and the
+        size groups of batches) or separate y, z, y passes."""
         self._check(self.L.hmc_set_plane_pass(self.ctx, int(bool(enable))))
 
     def launch_config(self):
