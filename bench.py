@@ -528,7 +528,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the sampler runs on a single MI355X "
-              "(chains or slabs would shard across GPUs, which this build does not do)",
+              "(chains or slabs would shard across GPUs; the library runs on one)",
               file=sys.stderr)
         sys.exit(2)
     if args.oracle_timing:

@@ -35,7 +35,7 @@
  *    synchronise the stream before returning.
  *  - Errors: every call returns hmc_status.  HMC_EINVAL: bad shape, size or
  *    null pointer; HMC_ENOMEM: workspace too small; HMC_EDEVICE: a HIP call
- *    failed; HMC_EUNSUPPORTED: a valid request this build does not implement;
+ *    failed; HMC_EUNSUPPORTED: a valid request the library does not implement;
  *    HMC_ENUMERIC: non-finite energy (the trajectory is rejected and the state
  *    restored).  hmc_last_error() returns a static description.  A context is
  *    not thread-safe; use one per stream.
