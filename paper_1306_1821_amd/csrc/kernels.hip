@@ -1135,7 +1135,9 @@ __device__ __forceinline__ void yzpass(const ChainDev& d, int x, const ZArgs a, 
   const int b = tid % PY, t = tid / PY;   // column phase: pencil b of each group, its thread t
   const int r = tid / TZ, tz = tid % TZ;  // row phase: row r of the chunk, its thread tz
   // twiddles staged in LDS: W_M^i (i < M), W_N^k (k < M), then W_N^i (i < N) for the
-  // y transforms (read from LDS, they are not kept in registers across the phases)
+  // y transforms (read from LDS, they are not kept in registers across the phases);
+  // a transform stage reads the entries at powers of two of the radix index and forms
+  // the others by complex products (fewer LDS reads than one read per twiddle)
   const float2* twM = stw;
   const float2* twN = stw + M;
   const float2* twy = stw + N;
@@ -1177,9 +1179,9 @@ __device__ __forceinline__ void yzpass(const ChainDev& d, int x, const ZArgs a, 
   static_for<0, G>([&](auto gc) {
     constexpr int g = decltype(gc)::value;
     if constexpr (g < GR) {
-      fft_dtw<N, TY, -1>(v[g], lds + b, ESY, t, true, twy, typename C::RLY{});
+      fft<N, TY, -1>(v[g], lds + b, ESY, t, true, twy, typename C::RLY{});
     } else {
-      fft_dtw<N, TY, -1>(u[g - GR], lds + b, ESY, t, true, twy, typename C::RLY{});
+      fft<N, TY, -1>(u[g - GR], lds + b, ESY, t, true, twy, typename C::RLY{});
 #pragma unroll
       for (int e = 0; e < EY; ++e) Ls[(t + TY * e) * LS + (g - GR) * PY + b] = u[g - GR][e];
     }
@@ -1224,7 +1226,7 @@ __device__ __forceinline__ void yzpass(const ChainDev& d, int x, const ZArgs a, 
     }
     xr[EZ] = make_float2(xr[0].y, 0.f);  // lane 0: X_M from the packed column (X_0 = Re xr[0])
     c2r_pre<N, TZ, EZ>(xr, w, Lr, tz, twN);
-    zfft_dtw<M, TZ, -1, typename C::RLZ>(w, Lr, tz, true, twM);
+    zfft<M, TZ, -1, typename C::RLZ>(w, Lr, tz, true, twM);
 #pragma unroll
     for (int e = 0; e < EZ; ++e) {
       const float2 xv = w[e];
@@ -1235,7 +1237,7 @@ __device__ __forceinline__ void yzpass(const ChainDev& d, int x, const ZArgs a, 
       w[e] = make_float2(al[e].x * xv.x - be[e].x, al[e].y * xv.y - be[e].y);
     }
     if constexpr (q + 1 < NCH) load_ab(q + 1);
-    zfft_dtw<M, TZ, +1, typename C::RLZ>(w, Lr, tz, true, twM);
+    zfft<M, TZ, +1, typename C::RLZ>(w, Lr, tz, true, twM);
     float x0 = 0.f;
     r2c_post<N, TZ, EZ>(w, Lr, tz, true, twN, [&](int k, float2 X) {
       if (k == 0)
@@ -1260,7 +1262,7 @@ __device__ __forceinline__ void yzpass(const ChainDev& d, int x, const ZArgs a, 
   static_for<0, G>([&](auto gc) {
     constexpr int g = decltype(gc)::value;
     if constexpr (g < GR) {
-      fft_dtw<N, TY, +1>(v[g], lds + b, ESY, t, true, twy, typename C::RLY{});
+      fft<N, TY, +1>(v[g], lds + b, ESY, t, true, twy, typename C::RLY{});
       if constexpr (g == 0) {
         // A_k = (Z_k + conj Z_-k) / 2 -> kz = 0, B_k = -i (Z_k - conj Z_-k) / 2 -> kz = M
         if (b == 0) {
@@ -1287,7 +1289,7 @@ __device__ __forceinline__ void yzpass(const ChainDev& d, int x, const ZArgs a, 
     } else {
 #pragma unroll
       for (int e = 0; e < EY; ++e) u[g - GR][e] = Ls[(t + TY * e) * LS + (g - GR) * PY + b];
-      fft_dtw<N, TY, +1>(u[g - GR], lds + b, ESY, t, true, twy, typename C::RLY{});
+      fft<N, TY, +1>(u[g - GR], lds + b, ESY, t, true, twy, typename C::RLY{});
 #pragma unroll
       for (int e = 0; e < EY; ++e) gsti(at(g, e), toff, u[g - GR][e]);
     }
