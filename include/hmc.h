@@ -238,10 +238,13 @@ hmc_status hmc_set_launch(hmc_ctx* ctx, int32_t pass_class, int32_t grid);
 
 /* Radix plan of the transforms of a pass class (0 the k-space step pass, 1 the
  * y passes, 2 the real-space force pass) in single-size launches of grids of
- * 64^3, 128^3, 192^3 and 256^3: plan 0 (default) or one of two alternative
- * factorisations of the same pencil shape (same tiles, LDS and memory access;
- * different stage counts and LDS exchanges), 0 <= plan < 3.  Other grid sizes
- * and mixed-size launches use plan 0.  A plan changes the rounding of the
+ * 64^3, 128^3, 192^3 and 256^3: plan 0 (default), one of two alternative
+ * factorisations of the same pencil shape (plans 1, 2: same tiles, LDS and memory
+ * access; different stage counts and LDS exchanges), or, at 64^3, 128^3 and
+ * 256^3, another tile shape for the step and y passes (plan 3: twice the threads
+ * per pencil and 512-thread workgroups at the same pencils per workgroup, so the
+ * same tiles; plan 3 is plan 0 elsewhere), 0 <= plan < 4.  Other grid sizes and
+ * mixed-size launches use plan 0.  The fused plane pass has one plan.  A plan changes the rounding of the
  * transforms (results agree with plan 0 to float32 rounding, not bitwise);
  * results are reproducible for a fixed plan.  Captured graphs are dropped.
  * HMC_EINVAL on a bad class or plan. */

@@ -353,8 +353,9 @@ class Sampler:
         self._check(self.L.hmc_set_launch(self.ctx, int(pass_class), int(grid)))
 
     def set_plan(self, pass_class, plan):
-        """Radix plan (0, 1, 2) of a pass class's transforms in single-size launches
-        of 64^3 .. 256^3 grids; plans other than 0 change rounding."""
+        """Radix plan (0, 1, 2) or tile shape (3: twice the threads per pencil at
+        64^3, 128^3, 256^3) of a pass class's transforms in single-size launches of
+        64^3 .. 256^3 grids; plans other than 0 change rounding."""
         self._check(self.L.hmc_set_plan(self.ctx, int(pass_class), int(plan)))
 
     def set_plane_pass(self, enable=True):

@@ -217,14 +217,31 @@ template <> struct ZC<256> { static constexpr int T = 32, B = 8;  using RL = Rad
 template <> struct ZC<256> { static constexpr int T = 8, B = 32;  using RL = Radices<16, 8>; };
 #endif
 
-// Radix plans of the single-size step passes.  Every plan keeps the pencil shape
-// (T threads, B pencils per workgroup), so tiles, LDS size and the memory access
-// pattern are the plan-independent; the transform's stage count and LDS exchanges
-// differ.  Plan 0 is the shape's default list; grids of 64^3 and more have two
-// alternatives that the autotuner times (hmc_autotune / hmc_set_plan).
+// Radix plans of the single-size step passes.  Every plan keeps the B pencils per
+// workgroup, so tiles, LDS size and the memory access pattern are plan-independent;
+// the transform's stage count and LDS exchanges differ.  Plan 0 is the shape's
+// default list; grids of 64^3 and more have two alternative radix lists at the same
+// T threads per pencil (plans 1, 2) and, at 64^3, 128^3 and 256^3, a tile shape with
+// twice the threads per pencil and half the values per thread (plan 3: 512-thread
+// workgroups, fewer registers per thread, one more exchange).  The autotuner times
+// them all (hmc_autotune / hmc_set_plan); plans only reach the k-space step pass,
+// the y passes and the real-space force pass (plan 3 is plan 0 there).
 
 template <int N> constexpr bool has_plans() { return N == 64 || N == 128 || N == 192 || N == 256; }
 template <int N, int P> struct XPlan { using RL = typename XC<N>::RL; };
+// threads per pencil of a plan (the shape's own T except for the plan-3 shapes)
+template <int N, int P> struct XShape { static constexpr int T = XC<N>::T; };
+template <> struct XPlan<64, 3>  { using RL = Radices<4, 4, 4>; };
+template <> struct XShape<64, 3> { static constexpr int T = 2 * XC<64>::T; };
+#if HMC_XCFG128 == 1
+template <> struct XPlan<128, 3>  { using RL = Radices<4, 4, 4, 2>; };
+template <> struct XShape<128, 3> { static constexpr int T = 2 * XC<128>::T; };
+#endif
+#if HMC_XCFG256 == 0
+template <> struct XPlan<256, 3>  { using RL = Radices<8, 8, 4>; };
+template <> struct XShape<256, 3> { static constexpr int T = 2 * XC<256>::T; };
+#endif
+template <int N, int P> constexpr int xthreads() { return XShape<N, P>::T * XC<N>::B; }
 template <> struct XPlan<64, 1>  { using RL = Radices<4, 4, 4>; };
 template <> struct XPlan<64, 2>  { using RL = Radices<2, 4, 8>; };
 #if HMC_XCFG128 == 1
@@ -602,7 +619,9 @@ __device__ __forceinline__ void xpass(const ChainDev& d, int lt, const XArgs a, 
                       float2* lds, double* red, bin_t* bins) {
   using C = XC<N>;
   using RL = typename XPlan<N, P>::RL;
-  constexpr int T = C::T, B = C::B, E = N / T, H = N / 2 + 1, ES = B + 1;
+  constexpr int T = XShape<N, P>::T, B = C::B, E = N / T, H = N / 2 + 1, ES = B + 1;
+  constexpr int NT = T * B;  // threads of the workgroup
+  static_assert(NT == kThreads || MODE == X_STEP, "other tile shapes only for the step pass");
   constexpr uint32_t stride = (uint32_t)N * H;
   const float2* tw = twall + tw_offset(N);
   const int tid = threadIdx.x, b = tid % B, t = tid / B;
@@ -623,7 +642,7 @@ __device__ __forceinline__ void xpass(const ChainDev& d, int lt, const XArgs a, 
 #if HMC_LDS_TAB
   // per-shell float tables of the chain in LDS (indexed gathers stay on chip)
   __shared__ float stf[4 * kMaxBins];
-  for (int i = tid; i < 4 * kMaxBins; i += kThreads) stf[i] = (i % kMaxBins) < d.nb ? gldf(d.tf + i) : 0.f;
+  for (int i = tid; i < 4 * kMaxBins; i += NT) stf[i] = (i % kMaxBins) < d.nb ? gldf(d.tf + i) : 0.f;
   __syncthreads();
   const float* const tf = stf;
 #else
@@ -803,7 +822,7 @@ __global__ void __launch_bounds__(kThreads) k_xpass(const ChainDev* __restrict__
 
 // single-size variant: every chain of the launch has this N (lower register use)
 template <int N, int MODE, int P = 0>
-__global__ void __launch_bounds__(kThreads) k_xpass_n(const ChainDev* __restrict__ ch, int nch,
+__global__ void __launch_bounds__((xthreads<N, P>())) k_xpass_n(const ChainDev* __restrict__ ch, int nch,
                                                        int total, XArgs a,
                                                        const float2* __restrict__ tw) {
   extern __shared__ float2 lds[];
@@ -827,7 +846,7 @@ __device__ __forceinline__ void ypass(const ChainDev& d, int lt, const float2* _
                                       int buf) {
   using C = XC<N>;
   using RL = typename XPlan<N, P>::RL;
-  constexpr int T = C::T, B = C::B, E = N / T, H = N / 2 + 1, ES = B + 1;
+  constexpr int T = XShape<N, P>::T, B = C::B, E = N / T, H = N / 2 + 1, ES = B + 1;
   const float2* tw = twall + tw_offset(N);
   const int tid = threadIdx.x, b = tid % B, t = tid / B;
   const int p = lt * B + b;
@@ -865,7 +884,7 @@ __global__ void __launch_bounds__(kThreads) k_ypass(const ChainDev* __restrict__
 }
 
 template <int N, int DIR, int P = 0>
-__global__ void __launch_bounds__(kThreads) k_ypass_n(const ChainDev* __restrict__ ch, int nch,
+__global__ void __launch_bounds__((xthreads<N, P>())) k_ypass_n(const ChainDev* __restrict__ ch, int nch,
                                                        int total, const float2* __restrict__ tw,
                                                        int buf) {
   extern __shared__ float2 lds[];
@@ -1716,6 +1735,11 @@ static void launch_x_n(int mode, dim3 g, dim3 bl, int lds, hipStream_t s, const 
           hipLaunchKernelGGL((k_xpass_n<N, X_STEP, 2>), g, bl, lds, s, ch, nch, total, a, tw);
           break;
         }
+        if (plan == 3) {
+          hipLaunchKernelGGL((k_xpass_n<N, X_STEP, 3>), g, dim3(xthreads<N, 3>()), lds, s, ch, nch,
+                             total, a, tw);
+          break;
+        }
       }
       hipLaunchKernelGGL((k_xpass_n<N, X_STEP>), g, bl, lds, s, ch, nch, total, a, tw);
       break;
@@ -1732,6 +1756,11 @@ static void launch_y_n(dim3 g, dim3 bl, int lds, hipStream_t s, const ChainDev* 
     }
     if (plan == 2) {
       hipLaunchKernelGGL((k_ypass_n<N, DIR, 2>), g, bl, lds, s, ch, nch, total, tw, buf);
+      return;
+    }
+    if (plan == 3) {
+      hipLaunchKernelGGL((k_ypass_n<N, DIR, 3>), g, dim3(xthreads<N, 3>()), lds, s, ch, nch, total,
+                         tw, buf);
       return;
     }
   }

@@ -53,7 +53,7 @@ bool supported_n(int n);
 // uniform_n: the N shared by every chain of the launch, or 0 for mixed sizes;
 // plan: radix plan (0 .. kPlanCount - 1) of the single-size step pass (X_STEP),
 // y passes and force pass (Z_GRAD) for N >= 64; other launches use plan 0
-constexpr int kPlanCount = 3;
+constexpr int kPlanCount = 4;
 void launch_xpass(int mode, const ChainDev* ch, int nch, int total, int lds, XArgs a,
                   const float2* tw, int grid_cap, hipStream_t s, int uniform_n, int plan = 0);
 void launch_ypass(int dir, const ChainDev* ch, int nch, int total, int lds, const float2* tw,

@@ -287,11 +287,13 @@ def test_batched_64_128_192_match_oracle(launch):
     s.close()
 
 
-@pytest.mark.parametrize("plan", [1, 2])
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("plan", [1, 2, 3])
 @pytest.mark.parametrize("n,box,nb", [s for s in SIZES if s[0] >= 64])
 def test_radix_plans_match_oracle(n, box, nb, plan):
-    """The alternative radix plans of the step, y and force passes: the gradient of
-    set_state (y passes, force pass) and, at 64^3 and 128^3, a trajectory (step
+    """The alternative radix plans and tile shape (plan 3: twice the threads per
+    pencil) of the step, y and force passes, with the separate y and real-space
+    passes: the gradient of set_state (y passes, force pass) and a trajectory (step
     pass) against the oracle; a plan's results are reproducible."""
     mk = plain_mock(n, box, nb, nsub=2)
     a32, b32 = coefficients32(mk)
@@ -302,6 +304,7 @@ def test_radix_plans_match_oracle(n, box, nb, plan):
     finals = []
     for rep in range(2):
         s = sampler_for(mk, eps=0.05, nsteps=6, seed=23)
+        s.set_plane_pass(False)
         for cls in range(3):
             s.set_plan(cls, plan)
         assert s.launch_config()[1] == [plan] * 3
@@ -311,7 +314,7 @@ def test_radix_plans_match_oracle(n, box, nb, plan):
         err = rel_l2(st["grad_k"], gk)
         print(f"N={n} plan {plan}: gradient rel-L2 {err:.2e}")
         assert err < 1e-5
-        if n <= 128:
+        if n <= 128 or plan == 3:
             before = s.state(0)
             dH, acc = s.trajectory(0)
             ref = hmc.trajectory(before["delta_k"].astype(np.complex128), post, 0.05, 6, 23, 0, 0)
