@@ -251,7 +251,7 @@ hmc_status hmc_set_launch(hmc_ctx* ctx, int32_t pass_class, int32_t grid);
 hmc_status hmc_set_plan(hmc_ctx* ctx, int32_t pass_class, int32_t plan);
 
 /* Fused y-z plane pass (enable = 1, the default) or separate passes (0) for
- * the gradient evaluations of grid sizes that have one (128^3, 192^3, 256^3):
+ * the gradient evaluations of grid sizes that have one (64^3 to 256^3):
  * contexts whose chains all have that size, and the size groups of a batch whose
  * y and real-space passes run one launch per size group (hmc_set_launch with
  * grid -1, the autotuner's usual choice).  The fused pass runs, per real-space x plane, the

@@ -359,7 +359,7 @@ class Sampler:
         self._check(self.L.hmc_set_plan(self.ctx, int(pass_class), int(plan)))
 
     def set_plane_pass(self, enable=True):
-        """Fused y-z plane pass (grid sizes 128, 192, 256: single-size contexts and the
+        """Fused y-z plane pass (grid sizes 64 to 256: single-size contexts and the
         size groups of batches) or separate y, z, y passes."""
         self._check(self.L.hmc_set_plane_pass(self.ctx, int(bool(enable))))
 

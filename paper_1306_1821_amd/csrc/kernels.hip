@@ -1105,6 +1105,16 @@ template <> struct PC<192> {
   using RLZ = Radices<4, 4, 6>;
   static constexpr int GL = 0;
 };
+// 64^3: the plane (64 x 33 complex, 17 KB) in registers of 256 threads (8 values
+// each, one pencil group, one z chunk); 4-thread z rows of the 32-point transform
+template <> struct PC<64> {
+  static constexpr int P = 256;
+  static constexpr int TY = 8;           // 8 values each
+  using RLY = Radices<8, 8>;
+  static constexpr int TZ = 4;           // 8 values each
+  using RLZ = Radices<8, 4>;
+  static constexpr int GL = 0;
+};
 // 128^3: the plane (128 x 65 complex, 66 KB) in registers of 512 threads (16 values
 // each, no group in LDS); 8-thread z rows of the 64-point half-length transform
 template <> struct PC<128> {
@@ -1334,7 +1344,7 @@ __global__ void __launch_bounds__(PC<N>::P) k_yzpass_n(const ChainDev* __restric
   yzpass<N>(ch[blockIdx.x / N], (int)(blockIdx.x % N), a, lds, stw, red);
 }
 
-bool plane_pass_supported(int n) { return n == 128 || n == 192 || n == 256; }
+bool plane_pass_supported(int n) { return n == 64 || n == 128 || n == 192 || n == 256; }
 void launch_yzpass(const ChainDev* ch, int nch, ZArgs a, const float2* tw, hipStream_t s, int n) {
   if (n == 256)
     hipLaunchKernelGGL(k_yzpass_n<256>, dim3(nch * 256), dim3(PC<256>::P), 0, s, ch, a, tw);
@@ -1342,6 +1352,8 @@ void launch_yzpass(const ChainDev* ch, int nch, ZArgs a, const float2* tw, hipSt
     hipLaunchKernelGGL(k_yzpass_n<192>, dim3(nch * 192), dim3(PC<192>::P), 0, s, ch, a, tw);
   else if (n == 128)
     hipLaunchKernelGGL(k_yzpass_n<128>, dim3(nch * 128), dim3(PC<128>::P), 0, s, ch, a, tw);
+  else if (n == 64)
+    hipLaunchKernelGGL(k_yzpass_n<64>, dim3(nch * 64), dim3(PC<64>::P), 0, s, ch, a, tw);
 }
 
 // ------------------------------------------------------------------ learned mass
