@@ -1160,6 +1160,9 @@ __device__ __forceinline__ void yzpass(const ChainDev& d, int x, const ZArgs a, 
   static_assert(M % PY == 0 && N % RZ == 0 && RZ % TY == 0 && EY % EC == 0, "plane tiling");
   static_assert(64 % TZ == 0 && TZ <= 16, "a z row sits in one DPP row group of a wavefront");
   static_assert(CR % TZ == 0 && GR >= 1, "register / LDS column split on a row-thread boundary");
+  // the plane's data energy goes to its own real-space tiles: a plane must cover whole
+  // tiles of the real-space pass (at 32^3 and below one tile spans several planes)
+  static_assert(N % ZC<N>::B == 0, "a plane covers whole real-space tiles");
   const int tid = threadIdx.x;
   const int b = tid % PY, t = tid / PY;   // column phase: pencil b of each group, its thread t
   const int r = tid / TZ, tz = tid % TZ;  // row phase: row r of the chunk, its thread tz
@@ -1354,6 +1357,7 @@ void launch_yzpass(const ChainDev* ch, int nch, ZArgs a, const float2* tw, hipSt
     hipLaunchKernelGGL(k_yzpass_n<128>, dim3(nch * 128), dim3(PC<128>::P), 0, s, ch, a, tw);
   else if (n == 64)
     hipLaunchKernelGGL(k_yzpass_n<64>, dim3(nch * 64), dim3(PC<64>::P), 0, s, ch, a, tw);
+
 }
 
 // ------------------------------------------------------------------ learned mass

@@ -212,7 +212,7 @@ def test_batched_mixed_sizes_match_oracle():
 @pytest.mark.parametrize("case,eps,nsteps", [("cfg3", 0.02, 4), (192, 0.03, 8), ("cfg2", 0.04, 8),
                                              (64, 0.05, 10)])
 def test_plane_pass_matches_separate_passes_and_oracle(case, eps, nsteps):
-    """At 256^3, 192^3, 128^3 and 64^3 the gradient evaluations run the fused y-z plane pass
+    """From 64^3 to 256^3 the gradient evaluations run the fused y-z plane pass
     (inverse y, C2R z, data force, R2C z, forward y with the plane on chip; the
     kz = 0 and kz = N/2 columns travel as one complex column).  Against the
     separate y, z, y passes and against the oracle: the gradient of set_state, the
