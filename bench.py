@@ -581,6 +581,7 @@ def main():
         s.trajectory(10_000 + i)
     torch.cuda.synchronize()
     dt_traj = time.perf_counter() - t1
+    print(f"[bench] {ntraj} bare trajectories in {dt_traj:.3f} s", file=sys.stderr, flush=True)
     # per-pass breakdown (events around every pass) on a few more trajectories
     s.timing(1)
     for i in range(3):
@@ -598,6 +599,8 @@ def main():
         eb.record()
     torch.cuda.synchronize()
     traj_ms = float(np.median([ea.elapsed_time(eb) for ea, eb in evs]))
+    print(f"[bench] 100 event-timed trajectories, median {traj_ms:.3f} ms", file=sys.stderr,
+          flush=True)
 
     steps = args.steps * spec["nsteps"]
     value = steps / dt
