@@ -270,9 +270,11 @@ hmc_status hmc_get_launch(hmc_ctx* ctx, int32_t* grid, int32_t* plan);
  * each candidate (for mixed-size batches one launch per size group, then one
  * launch over the batch with one workgroup per tile or 2, 3, 4, 5, 6, 8, 12
  * workgroups per compute unit) on the context's chains with HIP events and keeps
- * the fastest, then, when the chosen launches are single-size and a grid size
- * has alternative plans, times plans 1 and 2 at that grid and keeps the fastest
- * of the three (hmc_set_plan: a plan other than 0 changes rounding); chosen
+ * the fastest (in a batch with a size group that has a fused plane pass, the y
+ * and real-space classes keep one launch per size group, which the plane pass
+ * needs), then, when the chosen launches are single-size and a grid size has
+ * alternative plans, times plans 1 to 3 at that grid and keeps the fastest of
+ * the four (hmc_set_plan: a plan other than 0 changes rounding); chosen
  * (host [3], may be NULL) receives the grids in the form hmc_set_launch takes
  * (hmc_get_launch also returns the plans).  The state (delta_hat, p_hat, the
  * parameters) is unchanged; captured graphs are dropped. */

@@ -1116,6 +1116,11 @@ hmc_status hmc_autotune(hmc_ctx* c, int32_t reps, int32_t* chosen) {
     (void)hipEventElapsedTime(ms, a, b);
     return true;
   };
+  // batches whose size groups have a fused plane pass run it only when the y and
+  // real-space classes launch per size group, so those classes keep that launch
+  bool plane_groups = false;
+  for (auto& g : c->groups) plane_groups |= plane_pass_supported(g.n);
+  plane_groups &= c->plane_pass && c->uniform_n == 0;
   for (int cls = 0; cls < 3 && st == HMC_OK; ++cls) {
     float best = 0.f;
     int best_grid = 0;
@@ -1123,7 +1128,8 @@ hmc_status hmc_autotune(hmc_ctx* c, int32_t reps, int32_t* chosen) {
     c->plan[cls] = 0;
     // candidates: one launch per size group (batches of several sizes), then one
     // launch over the whole batch with each grid
-    for (int cand = c->groups.empty() ? 0 : -1; cand < (int)(sizeof(mult) / sizeof(int)); ++cand) {
+    const int last = plane_groups && cls > 0 ? 0 : (int)(sizeof(mult) / sizeof(int));
+    for (int cand = c->groups.empty() ? 0 : -1; cand < last; ++cand) {
       const bool grp = cand < 0;
       const int grid = grp ? 0 : mult[cand] * cus;
       if (!grp && mult[cand] > 0 && (grid >= class_tiles(c, cls) || grid % 8 != 0)) continue;
