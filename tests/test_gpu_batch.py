@@ -239,6 +239,40 @@ def test_joint_move_shortens_pk_correlation():
     assert j < nj
 
 
+@pytest.mark.timeout(400)
+def test_joint_move_leaves_power_posterior_invariant():
+    """The device counterpart of the oracle's stationarity pin (Appendix C,
+    eq. spec_posterior_MIXING_1; eq. INVERSE_GAMMA): with the proper prior
+    alpha = 0, sweeps of {density HMC, P draw, Nbar and b draws} with and without
+    the joint (P, delta) move leave the same posterior invariant, so the mean of
+    ln P per shell agrees within 4 standard errors (bulk ESS of four 8^3 chains per
+    arm, 6000 sweeps each).  A joint move whose HMC mass followed theta moved the
+    first shell's mean by half a posterior standard deviation in the oracle."""
+    m = mock("tiny8x2")
+    res = {}
+    for rj in (False, True):
+        specs = [chain_spec(m, eps=0.15, nsteps=8, seed=71, chain_id=c, rj=rj, alpha_prior=0.0)
+                 for c in range(4)]
+        s = Sampler(specs)
+        for i in range(4):
+            s.set_state(i, start_state(m)[0])
+        s.use_graph(True)
+        traces = [[] for _ in specs]
+        for sw in range(6000):
+            for i, o in enumerate(s.sweep(sw)):
+                traces[i].append(np.log(o["pk"]))
+        s.close()
+        res[rj] = np.array([t[200:] for t in traces])          # chains x samples x shells
+    a, b = res[False], res[True]
+    for mm in range(a.shape[2]):
+        ea, eb = dg.ess_bulk(a[:, :, mm]), dg.ess_bulk(b[:, :, mm])
+        se = np.sqrt(a[:, :, mm].var() / ea + b[:, :, mm].var() / eb)
+        d = b[:, :, mm].mean() - a[:, :, mm].mean()
+        print(f"shell {mm}: mean ln P without {a[:, :, mm].mean():.4f}, with {b[:, :, mm].mean():.4f}, "
+              f"difference {d / se:+.2f} SE (bulk ESS {ea:.0f}, {eb:.0f})", flush=True)
+        assert abs(d) < 4 * se, (mm, d / se)
+
+
 def test_field_moments_match_numpy():
     """hmc_field_moments: the running float64 mean and sum of squared deviations of
     delta_r over sweeps of two chains (pooled) equal numpy's on the stored states."""
