@@ -161,6 +161,44 @@ def test_trajectories_from_zero_match_oracle():
     s.close()
 
 
+@pytest.mark.timeout(300)
+def test_chain_matches_dense_wiener_posterior():
+    """Fixed P, b, Nbar at 8^3: the device's HMC draws have the closed-form Wiener
+    mean and covariance (eqs. Wiener_Posterior_psi, Wiener_Posterior_force; the dense
+    solve of tests/dense.py on the zero-mean subspace).  Draws whitened by that
+    covariance have zero mean and unit variance within their ESS-based errors."""
+    import dense
+    from test_oracle_hmc import _ess
+    mk = mock("tiny8x2")
+    cfg = mk["cfg"]
+    n = cfg.n
+    a32, b32 = coefficients32(mk)
+    lam_m = model.lambdas(mk["pk_init"], n, cfg.box)
+    mu, cov, Q, U = dense.wiener(n, lam_m, cfg.nb, a32.astype(np.float64), b32.astype(np.float64))
+    evals, evecs = np.linalg.eigh(U.T @ cov @ U)
+    T = (U @ evecs) / np.sqrt(evals)            # whitening map on the subspace
+    s = sampler_for(mk, eps=0.2, nsteps=12, seed=11, tau_mode=True)   # drawn lengths
+    s.set_coefficients(0, a32, b32)
+    s.set_state(0, mu.reshape(n, n, n).astype(np.float32))
+    samples, acc, nsamp = [], 0, 3000
+    for t in range(nsamp):
+        dH, a = s.trajectory(t)
+        acc += int(a[0])
+        samples.append(s.state(0)["delta_r"].reshape(-1).astype(np.float64))
+    s.close()
+    y = (np.array(samples) - mu) @ T                # iid N(0, 1) per column if exact
+    ess = np.array([_ess(y[:, j]) for j in range(y.shape[1])])
+    zmean = y.mean(axis=0) * np.sqrt(ess)
+    var = y.var(axis=0)
+    print(f"acceptance {acc / nsamp:.2f}, median ESS {np.median(ess):.0f}, max |z-mean| "
+          f"{np.max(np.abs(zmean)):.2f}, mean z^2 {np.mean(zmean ** 2):.2f}, mean variance {var.mean():.4f}")
+    assert acc / nsamp > 0.6
+    assert np.max(np.abs(zmean)) < 5.0
+    assert abs(np.mean(zmean ** 2) - 1.0) < 0.3
+    assert np.max(np.abs(var - 1.0) * np.sqrt(ess / 2.0)) < 6.0
+    assert abs(var.mean() - 1.0) < 0.03
+
+
 @pytest.mark.parametrize("eps,accepted", [(0.02, True), (0.8, False)])
 def test_gradient_cache_after_trajectory(eps, accepted):
     """After a trajectory, accepted (small step) or rejected (eps = 0.8: dH of 50-70 in
