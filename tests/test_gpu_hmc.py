@@ -179,7 +179,12 @@ def test_chain_matches_dense_wiener_posterior():
     T = (U @ evecs) / np.sqrt(evals)            # whitening map on the subspace
     s = sampler_for(mk, eps=0.2, nsteps=12, seed=11, tau_mode=True)   # drawn lengths
     s.set_coefficients(0, a32, b32)
-    s.set_state(0, mu.reshape(n, n, n).astype(np.float32))
+    # start at an exact draw of the posterior, so that the chain is stationary from the
+    # first trajectory (from the mean itself a slowly mixing mass needs thousands of
+    # trajectories to reach the posterior's spread)
+    z0 = np.random.default_rng(3).standard_normal(len(evals))
+    start = mu + (U @ evecs) @ (np.sqrt(evals) * z0)
+    s.set_state(0, start.reshape(n, n, n).astype(np.float32))
     samples, acc, nsamp = [], 0, 3000
     for t in range(nsamp):
         dH, a = s.trajectory(t)

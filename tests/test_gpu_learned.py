@@ -153,3 +153,50 @@ def test_diagonal_mass_trajectory_matches_oracle(case, eps, nsteps):
     ref = hmc.trajectory(before["delta_k"].astype(np.complex128), post, eps, nsteps, 47, 0, 8)
     assert rel_l2(s.state(0)["mom_k"], ref["p1"]) < 1e-4
     s.close()
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("kind", ["learned", "diagonal"])
+def test_mass_chain_matches_dense_wiener_posterior(kind):
+    """A mass only changes efficiency (the text after eq. Mass_matrix): with a
+    learned or diagonal mass from a random log-variance field, the device's draws at
+    8^3 (fixed P, b, Nbar) still have the closed-form Wiener mean and covariance of
+    the dense solve in tests/dense.py."""
+    import dense
+    from oracle import model
+    from test_oracle_hmc import _ess
+    mk = mock("tiny8x2")
+    cfg = mk["cfg"]
+    n = cfg.n
+    a32, b32 = coefficients32(mk)
+    lam_m = model.lambdas(mk["pk_init"], n, cfg.box)
+    mu, cov, Q, U = dense.wiener(n, lam_m, cfg.nb, a32.astype(np.float64), b32.astype(np.float64))
+    evals, evecs = np.linalg.eigh(U.T @ cov @ U)
+    T = (U @ evecs) / np.sqrt(evals)
+    logvar = 0.5 * np.random.default_rng(5).standard_normal((n, n, n))
+    s = Sampler([chain_spec(mk, eps=0.15, nsteps=12, seed=13, tau_mode=True)])
+    s.set_coefficients(0, a32, b32)
+    # start at an exact draw of the posterior, so that the chain is stationary from the
+    # first trajectory (from the mean itself a slowly mixing mass needs thousands of
+    # trajectories to reach the posterior's spread)
+    z0 = np.random.default_rng(3).standard_normal(len(evals))
+    start = mu + (U @ evecs) @ (np.sqrt(evals) * z0)
+    s.set_state(0, start.reshape(n, n, n).astype(np.float32))
+    s.set_mass(0, logvar, kind=kind)
+    samples, acc, nsamp = [], 0, 3000
+    for t in range(nsamp):
+        dH, a = s.trajectory(t)
+        acc += int(a[0])
+        samples.append(s.state(0)["delta_r"].reshape(-1).astype(np.float64))
+    s.close()
+    y = (np.array(samples) - mu) @ T
+    ess = np.array([_ess(y[:, j]) for j in range(y.shape[1])])
+    zmean = y.mean(axis=0) * np.sqrt(ess)
+    var = y.var(axis=0)
+    print(f"{kind}: acceptance {acc / nsamp:.2f}, median ESS {np.median(ess):.0f}, max |z-mean| "
+          f"{np.max(np.abs(zmean)):.2f}, mean z^2 {np.mean(zmean ** 2):.2f}, mean variance {var.mean():.4f}")
+    assert acc / nsamp > 0.5
+    assert np.max(np.abs(zmean)) < 5.0
+    assert abs(np.mean(zmean ** 2) - 1.0) < 0.3
+    assert np.max(np.abs(var - 1.0) * np.sqrt(ess / 2.0)) < 6.0
+    assert abs(var.mean() - 1.0) < 0.03
