@@ -617,7 +617,7 @@ def main():
     roof_p = {"bound": "hbm", "achieved": z_bytes / (z_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
               "unit": "GB/s", "frac": z_bytes / (z_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
               "traffic": measured_traffic("plane") if args.workload == "cfg3" else None,
-              "kernel": f"k_yzpass_n<{n}>", "avg_ms": z_ms, "launches": int(launches[2]),
+              "kernel": f"k_yzpass_n<{n}, false/true>", "avg_ms": z_ms, "launches": int(launches[2]),
               "bytes_per_launch": z_bytes}
     out = {
         "metric": f"leapfrog steps/s at {n}^3",

@@ -1147,7 +1147,9 @@ __device__ __forceinline__ void static_for(F&& f) {
   }
 }
 
-template <int N>
+// FULL = false: the plain leapfrog step's launch (no data energy, no real field out),
+// compiled without those branches (straight-line z-row code, no spilled registers)
+template <int N, bool FULL>
 __device__ __forceinline__ void yzpass(const ChainDev& d, int x, const ZArgs a, float2* lds,
                                        const float2* stw, double* red) {
   using C = PC<N>;
@@ -1221,7 +1223,11 @@ __device__ __forceinline__ void yzpass(const ChainDev& d, int x, const ZArgs a, 
 
   const float2* ap = reinterpret_cast<const float2*>(d.alpha);
   const float2* bp = reinterpret_cast<const float2*>(d.beta);
-  float* drout = (a.flags & ZF_WRITE_DRN) ? d.drn : (a.flags & ZF_WRITE_DR) ? d.dr : nullptr;
+  float* drout = !FULL                      ? nullptr
+                 : (a.flags & ZF_WRITE_DRN) ? d.drn
+                 : (a.flags & ZF_WRITE_DR)  ? d.dr
+                                            : nullptr;
+  const bool data = FULL && (a.flags & ZF_DATA);
   float2* const Lr = lds + r * RSZ;  // this thread's row of the chunk buffer
   double dat = 0.0;
   // alpha and beta of chunk q + 1 are loaded as soon as chunk q's force is formed,
@@ -1262,8 +1268,8 @@ __device__ __forceinline__ void yzpass(const ChainDev& d, int x, const ZArgs a, 
 #pragma unroll
     for (int e = 0; e < EZ; ++e) {
       const float2 xv = w[e];
-      if (drout) gsti(reinterpret_cast<float2*>(drout) + rq + TZ * e, ro, xv);  // trajectory ends
-      if (a.flags & ZF_DATA)
+      if (FULL && drout) gsti(reinterpret_cast<float2*>(drout) + rq + TZ * e, ro, xv);  // trajectory ends
+      if (data)
         dat += (0.5 * al[e].x * xv.x - be[e].x) * (double)xv.x +
                (0.5 * al[e].y * xv.y - be[e].y) * (double)xv.y;
       w[e] = make_float2(al[e].x * xv.x - be[e].x, al[e].y * xv.y - be[e].y);
@@ -1326,7 +1332,7 @@ __device__ __forceinline__ void yzpass(const ChainDev& d, int x, const ZArgs a, 
       for (int e = 0; e < EY; ++e) gsti(at(g, e), toff, u[g - GR][e]);
     }
   });
-  if (a.flags & ZF_DATA) {
+  if (data) {
     // the plane's data energy into the first of its z-pass tiles, zeros into the others
     constexpr int tpp = N / ZC<N>::B;
     const double sd = block_sum_w<P / 64>(dat, red);
@@ -1335,7 +1341,7 @@ __device__ __forceinline__ void yzpass(const ChainDev& d, int x, const ZArgs a, 
 }
 
 // single-size launch: N consecutive workgroups per chain, one per x plane
-template <int N>
+template <int N, bool FULL>
 __global__ void __launch_bounds__(PC<N>::P) k_yzpass_n(const ChainDev* __restrict__ ch, ZArgs a,
                                                         const float2* __restrict__ tw) {
   __shared__ float2 lds[PL<N>::TOTAL];
@@ -1344,20 +1350,25 @@ __global__ void __launch_bounds__(PC<N>::P) k_yzpass_n(const ChainDev* __restric
   for (int i = threadIdx.x; i < 2 * N; i += PC<N>::P)
     stw[i] = i < N / 2 ? tw[tw_offset(N / 2) + i] : i < N ? tw[tw_offset(N) + i - N / 2] : tw[tw_offset(N) + i - N];
   __syncthreads();
-  yzpass<N>(ch[blockIdx.x / N], (int)(blockIdx.x % N), a, lds, stw, red);
+  yzpass<N, FULL>(ch[blockIdx.x / N], (int)(blockIdx.x % N), a, lds, stw, red);
 }
 
 bool plane_pass_supported(int n) { return n == 64 || n == 128 || n == 192 || n == 256; }
+template <int N>
+static void launch_yz_n(const ChainDev* ch, int nch, ZArgs a, const float2* tw, hipStream_t s) {
+  if (a.flags & (ZF_DATA | ZF_WRITE_DR | ZF_WRITE_DRN))
+    hipLaunchKernelGGL((k_yzpass_n<N, true>), dim3(nch * N), dim3(PC<N>::P), 0, s, ch, a, tw);
+  else
+    hipLaunchKernelGGL((k_yzpass_n<N, false>), dim3(nch * N), dim3(PC<N>::P), 0, s, ch, a, tw);
+}
 void launch_yzpass(const ChainDev* ch, int nch, ZArgs a, const float2* tw, hipStream_t s, int n) {
-  if (n == 256)
-    hipLaunchKernelGGL(k_yzpass_n<256>, dim3(nch * 256), dim3(PC<256>::P), 0, s, ch, a, tw);
-  else if (n == 192)
-    hipLaunchKernelGGL(k_yzpass_n<192>, dim3(nch * 192), dim3(PC<192>::P), 0, s, ch, a, tw);
-  else if (n == 128)
-    hipLaunchKernelGGL(k_yzpass_n<128>, dim3(nch * 128), dim3(PC<128>::P), 0, s, ch, a, tw);
-  else if (n == 64)
-    hipLaunchKernelGGL(k_yzpass_n<64>, dim3(nch * 64), dim3(PC<64>::P), 0, s, ch, a, tw);
-
+  switch (n) {
+    case 256: launch_yz_n<256>(ch, nch, a, tw, s); break;
+    case 192: launch_yz_n<192>(ch, nch, a, tw, s); break;
+    case 128: launch_yz_n<128>(ch, nch, a, tw, s); break;
+    case 64: launch_yz_n<64>(ch, nch, a, tw, s); break;
+    default: break;
+  }
 }
 
 // ------------------------------------------------------------------ learned mass
