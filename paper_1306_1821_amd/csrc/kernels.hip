@@ -614,7 +614,10 @@ __device__ __forceinline__ void bins_flush(B* bins, double* dst, int nb, int str
 // col = tile B + b (ky = col / H, kz = col % H).  Idle lanes of the last tile read
 // column 0 (in bounds) and store nothing.  Every load of an element is issued
 // before its first use so that one wait covers them.
-template <int N, int MODE, int P = 0>
+// F = 1: the joint move's launches, compiled for their fixed flags without the
+// per-element flag branches: X_INV with XF_SCALE only, X_FWD with XF_SCALE | XF_DOT |
+// XF_NOSTORE (the shell dot, nothing stored)
+template <int N, int MODE, int P = 0, int F = 0>
 __device__ __forceinline__ void xpass(const ChainDev& d, int lt, const XArgs a, const float2* __restrict__ twall,
                       float2* lds, double* red, bin_t* bins) {
   using C = XC<N>;
@@ -667,7 +670,8 @@ __device__ __forceinline__ void xpass(const ChainDev& d, int lt, const XArgs a, 
 #endif
   };
 
-  const bool dot = (MODE == X_FWD) && (a.flags & XF_DOT);
+  static_assert(F == 0 || MODE == X_INV || MODE == X_FWD, "flag instantiations of X_INV, X_FWD");
+  const bool dot = (MODE == X_FWD) && (F == 1 || (a.flags & XF_DOT));
   if (dot) bins_zero(bins);
 
   if constexpr (MODE != X_INV) {
@@ -677,7 +681,15 @@ __device__ __forceinline__ void xpass(const ChainDev& d, int lt, const XArgs a, 
   }
 
   double acc0 = 0.0, acc1 = 0.0;
-  if constexpr (MODE == X_INV) {
+  if constexpr (MODE == X_INV && F == 1) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int me = shell(e);
+      const float2 x = gldi(dkb, offs(e));
+      const float s = norm * tf[kTScale + (me >= 0 ? me : 0)];
+      v[e] = me < 0 ? make_float2(0.f, 0.f) : cscale(x, s);
+    }
+  } else if constexpr (MODE == X_INV) {
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int me = shell(e);
@@ -686,6 +698,20 @@ __device__ __forceinline__ void xpass(const ChainDev& d, int lt, const XArgs a, 
       if ((a.flags & XF_SCALE) && me >= 0) s *= tf[kTScale + me];
       if ((a.flags & XF_PRIOR) && me >= 0) s *= rsqrtf(tf[kTInvLam + me]);  // sqrt(lambda_m)
       v[e] = me < 0 ? make_float2(0.f, 0.f) : cscale(x, s);
+    }
+  } else if constexpr (MODE == X_FWD && F == 1) {
+    // every delta_hat load issued together (idle lanes read column 0, in bounds)
+    float2 xk[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) xk[e] = gldi(dkb, offs(e));
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int me = shell(e);
+      const bool on = active && me >= 0;
+      const float2 g = cscale(v[e], norm);
+      const float sc = tf[kTScale + (me >= 0 ? me : 0)];
+      const double val = on ? wz * ((double)(sc * xk[e].x) * g.x + (double)(sc * xk[e].y) * g.y) : 0.0;
+      if (on) atomicAdd(&bins[((threadIdx.x >> 6) * kBinCopies + bin_copy<B>()) * kBinStride + me], (bin_t)val);
     }
   } else if constexpr (MODE == X_FWD) {
 #pragma unroll
@@ -821,7 +847,7 @@ __global__ void __launch_bounds__(kThreads) k_xpass(const ChainDev* __restrict__
 }
 
 // single-size variant: every chain of the launch has this N (lower register use)
-template <int N, int MODE, int P = 0>
+template <int N, int MODE, int P = 0, int F = 0>
 __global__ void __launch_bounds__((xthreads<N, P>())) k_xpass_n(const ChainDev* __restrict__ ch, int nch,
                                                        int total, XArgs a,
                                                        const float2* __restrict__ tw) {
@@ -836,7 +862,7 @@ __global__ void __launch_bounds__((xthreads<N, P>())) k_xpass_n(const ChainDev* 
     const int tile = w.cur;
     const int c = find_chain(ch, nch, tile, kTileXY);
     const ChainDev& d = ch[c];
-    xpass<N, MODE, P>(d, tile - d.tb[kTileXY], a, tw, lds, red, bins);
+    xpass<N, MODE, P, F>(d, tile - d.tb[kTileXY], a, tw, lds, red, bins);
   }
 }
 
@@ -1749,8 +1775,18 @@ template <int N>
 static void launch_x_n(int mode, dim3 g, dim3 bl, int lds, hipStream_t s, const ChainDev* ch,
                        int nch, int total, XArgs a, const float2* tw, int plan) {
   switch (mode) {
-    case X_INV: hipLaunchKernelGGL((k_xpass_n<N, X_INV>), g, bl, lds, s, ch, nch, total, a, tw); break;
-    case X_FWD: hipLaunchKernelGGL((k_xpass_n<N, X_FWD>), g, bl, lds, s, ch, nch, total, a, tw); break;
+    case X_INV:
+      if (a.flags == XF_SCALE)
+        hipLaunchKernelGGL((k_xpass_n<N, X_INV, 0, 1>), g, bl, lds, s, ch, nch, total, a, tw);
+      else
+        hipLaunchKernelGGL((k_xpass_n<N, X_INV>), g, bl, lds, s, ch, nch, total, a, tw);
+      break;
+    case X_FWD:
+      if (a.flags == (XF_SCALE | XF_DOT | XF_NOSTORE))
+        hipLaunchKernelGGL((k_xpass_n<N, X_FWD, 0, 1>), g, bl, lds, s, ch, nch, total, a, tw);
+      else
+        hipLaunchKernelGGL((k_xpass_n<N, X_FWD>), g, bl, lds, s, ch, nch, total, a, tw);
+      break;
     case X_START: hipLaunchKernelGGL((k_xpass_n<N, X_START>), g, bl, lds, s, ch, nch, total, a, tw); break;
     case X_STEP:
       if constexpr (has_plans<N>()) {
