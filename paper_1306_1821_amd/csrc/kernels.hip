@@ -614,9 +614,8 @@ __device__ __forceinline__ void bins_flush(B* bins, double* dst, int nb, int str
 // col = tile B + b (ky = col / H, kz = col % H).  Idle lanes of the last tile read
 // column 0 (in bounds) and store nothing.  Every load of an element is issued
 // before its first use so that one wait covers them.
-// F = 1: the joint move's launches, compiled for their fixed flags without the
-// per-element flag branches: X_INV with XF_SCALE only, X_FWD with XF_SCALE | XF_DOT |
-// XF_NOSTORE (the shell dot, nothing stored)
+// F = 1: the joint move's shell-dot launch (X_FWD with XF_SCALE | XF_DOT | XF_NOSTORE,
+// nothing stored), compiled for those flags without the per-element flag branches
 template <int N, int MODE, int P = 0, int F = 0>
 __device__ __forceinline__ void xpass(const ChainDev& d, int lt, const XArgs a, const float2* __restrict__ twall,
                       float2* lds, double* red, bin_t* bins) {
@@ -670,7 +669,7 @@ __device__ __forceinline__ void xpass(const ChainDev& d, int lt, const XArgs a, 
 #endif
   };
 
-  static_assert(F == 0 || MODE == X_INV || MODE == X_FWD, "flag instantiations of X_INV, X_FWD");
+  static_assert(F == 0 || MODE == X_FWD, "flag instantiation of X_FWD only");
   const bool dot = (MODE == X_FWD) && (F == 1 || (a.flags & XF_DOT));
   if (dot) bins_zero(bins);
 
@@ -681,15 +680,7 @@ __device__ __forceinline__ void xpass(const ChainDev& d, int lt, const XArgs a, 
   }
 
   double acc0 = 0.0, acc1 = 0.0;
-  if constexpr (MODE == X_INV && F == 1) {
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int me = shell(e);
-      const float2 x = gldi(dkb, offs(e));
-      const float s = norm * tf[kTScale + (me >= 0 ? me : 0)];
-      v[e] = me < 0 ? make_float2(0.f, 0.f) : cscale(x, s);
-    }
-  } else if constexpr (MODE == X_INV) {
+  if constexpr (MODE == X_INV) {
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int me = shell(e);
@@ -1775,12 +1766,7 @@ template <int N>
 static void launch_x_n(int mode, dim3 g, dim3 bl, int lds, hipStream_t s, const ChainDev* ch,
                        int nch, int total, XArgs a, const float2* tw, int plan) {
   switch (mode) {
-    case X_INV:
-      if (a.flags == XF_SCALE)
-        hipLaunchKernelGGL((k_xpass_n<N, X_INV, 0, 1>), g, bl, lds, s, ch, nch, total, a, tw);
-      else
-        hipLaunchKernelGGL((k_xpass_n<N, X_INV>), g, bl, lds, s, ch, nch, total, a, tw);
-      break;
+    case X_INV: hipLaunchKernelGGL((k_xpass_n<N, X_INV>), g, bl, lds, s, ch, nch, total, a, tw); break;
     case X_FWD:
       if (a.flags == (XF_SCALE | XF_DOT | XF_NOSTORE))
         hipLaunchKernelGGL((k_xpass_n<N, X_FWD, 0, 1>), g, bl, lds, s, ch, nch, total, a, tw);
